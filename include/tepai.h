@@ -1,0 +1,215 @@
+/*
+ * tepai.h -- C ABI of libtepai, batched MPS TE-PAI on one MI355X (gfx950).
+ *
+ * The library estimates <O>(T) for a Hamiltonian H = sum_k c_k h_k (Pauli
+ * terms h_k) with the TE-PAI protocol of Hasselgren & Koczor, "Quantum-inspired
+ * classical simulation through randomized time evolution" (sec. "TE-PAI",
+ * protocol steps 1-3): each rotation R_k(theta_k), theta_k = 2 c_k T / N, of
+ * the N-step first-order Trotter circuit is replaced at random by I,
+ * R_k(sign(theta_k) Delta) or R_k(pi) (appendix "PAI & TE-PAI", eqs.
+ * settings and gammas); every sampled circuit is simulated as a matrix
+ * product state with bond cap chi (sec. "Resource model and cost metrics":
+ * two-site update, SVD re-factorisation, truncation to the chi largest
+ * singular values); the per-sample values are weighted by ||g||_1 sign(g_l)
+ * and averaged (Statement 2).
+ *
+ * Conventions for every entry point:
+ *  - All pointers are owned by the caller.  The library copies what it needs
+ *    from host inputs before returning and keeps no pointer to them.
+ *  - Pointers named d_* and `workspace` are device pointers on the handle's
+ *    device; all others are host pointers.
+ *  - Errors are reported by the return code only; no exception crosses the
+ *    ABI.  On error the outputs are unspecified and tepai_last_error(h)
+ *    describes the failure.
+ *  - A handle must not be used by two host threads at once.
+ *  - Sampling is deterministic: the same problem and seed give bit-identical
+ *    circuits and signs on every run.
+ *
+ * Readings of the paper that the library implements (where it is silent):
+ *  - time order of the rotations is the order of `terms`, repeated for each
+ *    of the N Trotter steps;
+ *  - a rotation with |theta_k| > Delta is split into m = ceil(|theta_k|/Delta)
+ *    equal sub-rotations (the paper assumes |theta| <= Delta);
+ *  - consecutive sampled gates on one qubit pair form one two-site update
+ *    (one truncated SVD); runs end at Trotter-step boundaries;
+ *  - a two-qubit gate on non-adjacent sites (the ring's wrap bond) is
+ *    applied by carrying the upper qubit down with SWAP updates (each
+ *    truncated) and back up again;
+ *  - a two-site update keeps min(chi, #{sigma_i > svd_cutoff * sigma_0})
+ *    singular values and renormalises them; the orthogonality centre is
+ *    moved by single-site SVDs that drop sigma_i <= svd_cutoff * sigma_0.
+ */
+#ifndef TEPAI_H
+#define TEPAI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TEPAI_OK = 0,
+  TEPAI_EINVAL = -1,    /* malformed argument (null pointer, bad qubit, ...) */
+  TEPAI_ERANGE = -2,    /* value out of range (Delta not in (0,pi), N = 0, chi = 0 ...) */
+  TEPAI_ENOMEM = -3,    /* workspace or output capacity too small */
+  TEPAI_EDEVICE = -4,   /* HIP runtime error */
+  TEPAI_ENUMERIC = -5   /* non-finite result */
+} tepai_status;
+
+enum { TEPAI_PAULI_I = 0, TEPAI_PAULI_X = 1, TEPAI_PAULI_Y = 2, TEPAI_PAULI_Z = 3 };
+
+/* Gate setting codes of a sampled rotation (appendix "PAI & TE-PAI", eq. settings). */
+enum { TEPAI_SET_A = 0, TEPAI_SET_B = 1, TEPAI_SET_C = 2 };
+
+/* Storage / arithmetic precision of the MPS path. */
+enum { TEPAI_FP64 = 0 };
+
+/* One Hamiltonian term c * P_0(q_0) [P_1(q_1)]; nq = 1 or 2.  Two-qubit
+ * terms must act on neighbours of the ring: |q0 - q1| = 1 or {0, n-1}. */
+typedef struct {
+  uint32_t nq;
+  uint32_t qubit[2];
+  uint8_t pauli[2];     /* TEPAI_PAULI_X/Y/Z */
+  uint8_t pad[6];
+  double coeff;
+} tepai_term;
+
+/* One weighted Pauli string coeff * prod_i P_i(q_i) contributing to
+ * observable number `observable`; each observable is the sum of its strings. */
+typedef struct {
+  uint32_t n_ops;               /* 1 .. 8 */
+  uint32_t observable;
+  const uint32_t* qubits;       /* [n_ops], distinct */
+  const uint8_t* paulis;        /* [n_ops], TEPAI_PAULI_X/Y/Z */
+  double coeff;
+} tepai_pauli_string;
+
+typedef struct {
+  uint32_t n_qubits;            /* 2 .. 256 */
+  uint32_t n_terms;
+  const tepai_term* terms;      /* time order inside one Trotter step */
+  double total_time;            /* T >= 0 */
+  uint32_t trotter_steps;       /* N >= 1 */
+  double delta;                 /* PAI angle, 0 < Delta < pi */
+  uint64_t n_samples;           /* N_s */
+  uint64_t sample_offset;       /* global index of the first sample */
+  uint64_t seed;
+  uint32_t chi_max;             /* bond cap, 1 .. 256 */
+  const uint32_t* chi_per_sample; /* nullable; [n_samples] caps <= chi_max */
+  double svd_cutoff;            /* relative singular-value floor, >= 0 */
+  const uint8_t* initial_bits;  /* [n_qubits] computational-basis start, 0/1 */
+  uint32_t n_obs;
+  uint32_t n_strings;
+  const tepai_pauli_string* strings;
+  uint32_t precision;           /* TEPAI_FP64 */
+  uint32_t flags;               /* reserved, 0 */
+} tepai_problem;
+
+/* Per-sample counters (cost model of eq. Wsample and truncation record). */
+typedef struct {
+  uint64_t n_gates;             /* non-identity sampled gates */
+  uint64_t updates;             /* truncated two-site updates (incl. SWAPs) */
+  uint64_t swap_updates;
+  uint64_t shifts;              /* single-site centre shifts */
+  uint64_t jacobi_sweeps;       /* over all factorisations */
+  uint64_t nonconverged;        /* factorisations that hit the sweep cap */
+  uint64_t ties;                /* updates with sigma_{k-1}-sigma_k <= 1e-10 sigma_0 at a chi cut */
+  double sum_chi3;              /* sum over updates of chi_mid^3 */
+  double nominal_flops;         /* Golub-Reinsch count of all updates */
+  double discarded;             /* sum of discarded squared Schmidt weight */
+  double max_discarded;
+  double min_gap;               /* min (sigma_{k-1}-sigma_k)/sigma_0 at a cut */
+  int32_t sign;                 /* (-1)^(number of C settings) */
+  uint32_t layer;               /* Trotter steps applied so far */
+  uint32_t max_bond;
+  uint32_t flags;               /* bit 0: non-finite value seen */
+} tepai_sample_stats;
+
+typedef struct tepai_handle tepai_handle;
+typedef struct tepai_batch tepai_batch;
+
+/* Create a handle bound to HIP device `device`.  Fails with TEPAI_EDEVICE
+ * when the device is absent or is not gfx950. */
+tepai_status tepai_create(tepai_handle** out, int device);
+void tepai_destroy(tepai_handle* h);
+/* Message of the last failure on this handle ("" if none).  Valid until the
+ * next call on the handle. */
+const char* tepai_last_error(const tepai_handle* h);
+
+/* Check a problem description (ranges, qubit indices, ring adjacency).
+ * Returns TEPAI_OK or the first error found. */
+tepai_status tepai_validate(tepai_handle* h, const tepai_problem* p);
+
+/* The per-rotation PAI table the sampler uses (host computation).
+ * Row r of the L_eff rows: source term index term[r], signed sub-rotation
+ * angle theta[r] = 2 c T / (N m), gamma[3r..3r+2] = gamma_1..3(|theta|)
+ * (eq. gammas), thresholds[2r], thresholds[2r+1] = floor(p_1 2^63),
+ * floor((p_1+p_2) 2^63) (2^63 when the mass reaches 1).  A setting is
+ * drawn from v = u >> 1 of a Philox4x32-10 64-bit uniform u as A if
+ * v < t1, B if v < t2, else C.  *log_g1_step = sum_r log ||gamma_r||_1,
+ * so log ||g||_1 = N * *log_g1_step (eq. overhead-bound).  `capacity` is the
+ * row capacity of the output arrays; *l_eff is set even when it is too small
+ * (then TEPAI_ENOMEM). */
+tepai_status tepai_pai_table(tepai_handle* h, const tepai_problem* p, uint32_t capacity,
+                             uint32_t* l_eff, uint32_t* term, double* theta, double* gamma,
+                             uint64_t* thresholds, double* log_g1_step, uint32_t* n_split_terms);
+
+/* Sample the circuits of samples sample_offset+first .. +first+count-1,
+ * first `layers` Trotter steps (0 = all N), on the GPU.  Sample i's gates
+ * are words[offsets[i] .. offsets[i+1]-1], each word = g * 4 + setting with
+ * g = j * L_eff + r the flat rotation index (time order) and setting
+ * TEPAI_SET_B or TEPAI_SET_C; signs[i] = (-1)^(#C).  offsets has count+1
+ * entries and is always written; if offsets[count] > capacity the call
+ * returns TEPAI_ENOMEM without writing words.  Host pointers. */
+tepai_status tepai_sample_circuits(tepai_handle* h, const tepai_problem* p, uint64_t first,
+                                   uint64_t count, uint32_t layers, uint64_t capacity,
+                                   uint64_t* offsets, uint32_t* words, int8_t* signs);
+
+/* Device workspace needed by a batch of `count` samples of problem p. */
+tepai_status tepai_workspace_size(tepai_handle* h, const tepai_problem* p, uint32_t count,
+                                  size_t* bytes);
+
+/* Start a batch: samples sample_offset+first .. +first+count-1, each in the
+ * initial product state, in the caller's device `workspace` (>= the size
+ * reported by tepai_workspace_size; 256-byte aligned).  Work is queued on
+ * `hip_stream` (a hipStream_t, NULL = default stream); the library allocates
+ * no device memory for a batch.  The batch object is a small host record;
+ * destroy it with tepai_batch_destroy (the workspace stays the caller's). */
+tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_t first,
+                                uint32_t count, void* workspace, size_t ws_bytes,
+                                void* hip_stream, tepai_batch** out);
+/* Apply the next `n_layers` Trotter steps of every sample's sampled circuit
+ * (sampling fused: each sample draws its own gate settings). */
+tepai_status tepai_batch_evolve(tepai_batch* b, uint32_t n_layers);
+/* Read out the observables of every sample at its current step j:
+ * d_values[s * n_obs + o] = <O_o> of sample s (normalised state), and
+ * d_weights[s] = sign_s * ||g||_1(j) with ||g||_1(j) = exp(j * log_g1_step),
+ * the weight of the TE-PAI sample made of the first j steps. */
+tepai_status tepai_batch_observe(tepai_batch* b, double* d_values, double* d_weights);
+/* Copy the per-sample counters to the host ([count] records); synchronises
+ * the batch's stream. */
+tepai_status tepai_batch_stats(tepai_batch* b, tepai_sample_stats* stats);
+void tepai_batch_destroy(tepai_batch* b);
+
+/* Weighted reduction on the device (Statement 2): x_s = w_s v_s,
+ * d_mean[o] = sum_s x_so / count, d_std_err[o] = sqrt(var_o / count) with the
+ * ddof=1 sample variance (NaN when count < 2), fixed summation order. */
+tepai_status tepai_reduce(tepai_handle* h, uint64_t count, uint32_t n_obs, const double* d_values,
+                          const double* d_weights, double* d_mean, double* d_std_err,
+                          void* hip_stream);
+
+/* The whole estimator, synchronous, host outputs: mean[n_obs], std_err[n_obs],
+ * weights[n_samples]; values[n_samples * n_obs] and stats[n_samples] are
+ * optional (NULL to skip).  Allocates and frees its own device memory and
+ * processes the samples in batches of at most `batch` (0 = library choice). */
+tepai_status tepai_run(tepai_handle* h, const tepai_problem* p, uint32_t batch, double* mean,
+                       double* std_err, double* weights, double* values,
+                       tepai_sample_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TEPAI_H */

@@ -10,8 +10,8 @@ every path that claims parity with this oracle:
 1. Gates act in time order.  A single-qubit gate is applied exactly to its
    site tensor.
 2. Consecutive sampled gates on the same qubit pair, with no other gate on
-   either qubit in between, are multiplied into one 4x4 operator and applied
-   as ONE two-site update (one truncated SVD).  A run made only of pi
+   either qubit in between and within one Trotter step, are multiplied into
+   one 4x4 operator and applied as ONE two-site update (one truncated SVD).  A run made only of pi
    rotations (C = -i P (x) P) is a product of local unitaries and is applied
    to the two site tensors without an SVD.
 3. A two-qubit operator whose qubits sit on non-adjacent sites (the ring's
@@ -79,8 +79,9 @@ def flip_pair(G: np.ndarray) -> np.ndarray:
 
 
 class _Pending:
-    def __init__(self, qa: int, qb: int):
+    def __init__(self, qa: int, qb: int, layer: int):
         self.qa, self.qb = qa, qb
+        self.layer = layer
         self.M = np.eye(4, dtype=complex)
         self.has_b = False
         self.La = np.eye(2, dtype=complex)
@@ -143,6 +144,10 @@ def build_schedule(problem, table, circuit, chi: Optional[int] = None) -> Tuple[
 
     pending: Optional[_Pending] = None
     for g, setting in zip(circuit.draws.tolist(), circuit.settings.tolist()):
+        layer = g // L
+        if pending is not None and pending.layer != layer:
+            flush(pending)
+            pending = None
         row = table.rows[g % L]
         term = problem.terms[row.term]
         U = setting_operator(term.paulis, row.theta, problem.delta, setting)
@@ -158,7 +163,7 @@ def build_schedule(problem, table, circuit, chi: Optional[int] = None) -> Tuple[
             flush(pending)
             pending = None
         if pending is None:
-            pending = _Pending(qa, qb)
+            pending = _Pending(qa, qb, layer)
         if (qa, qb) != (pending.qa, pending.qb):
             U = flip_pair(U)
             pa, pb = term.paulis[1], term.paulis[0]

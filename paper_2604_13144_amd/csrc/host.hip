@@ -1,0 +1,536 @@
+// Host side of libtepai: validation, the PAI table, workspace layout, the
+// batch interface and the synchronous estimator.  Every C entry point of
+// tepai.h is defined here.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tepai_internal.h"
+
+struct tepai_handle {
+  int device = 0;
+  std::string err;
+};
+
+namespace tepai {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr uint64_t kThresholdOne = 1ull << 63;
+
+tepai_status fail(tepai_handle* h, tepai_status st, const std::string& msg) {
+  if (h) h->err = msg;
+  return st;
+}
+
+#define TEPAI_HIP(h, expr)                                                           \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail((h), TEPAI_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// ------------------------------------------------------------ PAI table
+// gamma_1..3 at angle |theta| for PAI angle Delta (appendix "PAI & TE-PAI",
+// eq. gammas).
+void pai_gammas(double t, double d, double g[3]) {
+  g[0] = std::cos(t / 2.0) * std::sin(d / 2.0 - t / 2.0) / std::sin(d / 2.0);
+  g[1] = std::sin(t) / std::sin(d);
+  g[2] = -std::sin(t / 2.0) * std::sin(d / 2.0 - t / 2.0) / std::cos(d / 2.0);
+}
+
+uint64_t threshold(double p) {
+  if (p >= 1.0) return kThresholdOne;
+  if (p <= 0.0) return 0;
+  return (uint64_t)(p * 9223372036854775808.0);   // p * 2^63, exact scaling
+}
+
+struct HostRow {
+  uint32_t term;
+  double theta;
+  double g[3];
+  double norm1;
+  uint64_t t1, t2;
+};
+
+struct Table {
+  std::vector<HostRow> rows;
+  double log_step = 0.0;
+  uint32_t n_split = 0;
+};
+
+// theta_k = 2 c_k T / N (appendix "PAI & TE-PAI"); a rotation with
+// |theta_k| > Delta becomes ceil(|theta_k| / Delta) equal sub-rotations.
+Table build_table(const tepai_problem& p) {
+  Table t;
+  for (uint32_t k = 0; k < p.n_terms; ++k) {
+    const double theta = 2.0 * p.terms[k].coeff * p.total_time / (double)p.trotter_steps;
+    uint32_t m = 1;
+    if (std::fabs(theta) > p.delta) {
+      m = (uint32_t)std::ceil(std::fabs(theta) / p.delta);
+      t.n_split += 1;
+    }
+    HostRow r;
+    r.term = k;
+    r.theta = theta / (double)m;
+    pai_gammas(std::fabs(r.theta), p.delta, r.g);
+    r.norm1 = std::fabs(r.g[0]) + std::fabs(r.g[1]) + std::fabs(r.g[2]);
+    const double p1 = std::fabs(r.g[0]) / r.norm1, p2 = std::fabs(r.g[1]) / r.norm1;
+    r.t1 = threshold(p1);
+    r.t2 = threshold(p1 + p2);
+    for (uint32_t i = 0; i < m; ++i) t.rows.push_back(r);
+  }
+  for (const HostRow& r : t.rows) t.log_step += std::log(r.norm1);
+  return t;
+}
+
+std::vector<DevRow> device_rows(const tepai_problem& p, const Table& t) {
+  std::vector<DevRow> out(t.rows.size());
+  for (size_t i = 0; i < t.rows.size(); ++i) {
+    const HostRow& r = t.rows[i];
+    const tepai_term& term = p.terms[r.term];
+    const double phi = r.theta != 0.0 ? std::copysign(p.delta, r.theta) : p.delta;
+    DevRow d{};
+    d.t1 = r.t1;
+    d.t2 = r.t2;
+    d.cb = std::cos(phi / 2.0);
+    d.sb = std::sin(phi / 2.0);
+    d.nq = term.nq;
+    d.q0 = term.qubit[0];
+    d.q1 = term.nq == 2 ? term.qubit[1] : 0;
+    d.p0 = term.pauli[0];
+    d.p1 = term.nq == 2 ? term.pauli[1] : 0;
+    out[i] = d;
+  }
+  return out;
+}
+
+// ----------------------------------------------------------- validation
+tepai_status validate(tepai_handle* h, const tepai_problem* p) {
+  if (!p) return fail(h, TEPAI_EINVAL, "problem is NULL");
+  const uint32_t n = p->n_qubits;
+  if (n < 2 || n > (uint32_t)kMaxQubits) return fail(h, TEPAI_ERANGE, "n_qubits must be in [2, 256]");
+  if (!p->terms || p->n_terms == 0) return fail(h, TEPAI_EINVAL, "no Hamiltonian terms");
+  for (uint32_t k = 0; k < p->n_terms; ++k) {
+    const tepai_term& t = p->terms[k];
+    if (t.nq != 1 && t.nq != 2) return fail(h, TEPAI_EINVAL, "term " + std::to_string(k) + ": nq must be 1 or 2");
+    for (uint32_t i = 0; i < t.nq; ++i) {
+      if (t.qubit[i] >= n) return fail(h, TEPAI_EINVAL, "term " + std::to_string(k) + ": qubit out of range");
+      if (t.pauli[i] < 1 || t.pauli[i] > 3) return fail(h, TEPAI_EINVAL, "term " + std::to_string(k) + ": Pauli code must be X, Y or Z");
+    }
+    if (t.nq == 2) {
+      const uint32_t a = t.qubit[0], b = t.qubit[1];
+      const uint32_t d = a > b ? a - b : b - a;
+      if (!(d == 1 || (d == n - 1 && n > 2)))
+        return fail(h, TEPAI_EINVAL, "term " + std::to_string(k) + ": two-qubit terms must act on ring neighbours");
+    }
+    if (!std::isfinite(t.coeff)) return fail(h, TEPAI_ERANGE, "non-finite coefficient");
+  }
+  if (!std::isfinite(p->total_time) || p->total_time < 0.0) return fail(h, TEPAI_ERANGE, "total_time must be finite and >= 0");
+  if (p->trotter_steps == 0) return fail(h, TEPAI_ERANGE, "trotter_steps must be >= 1");
+  if (!(p->delta > 0.0 && p->delta < kPi)) return fail(h, TEPAI_ERANGE, "delta must lie in (0, pi)");
+  if (p->n_samples == 0) return fail(h, TEPAI_ERANGE, "n_samples must be >= 1");
+  if (p->sample_offset + p->n_samples > (1ull << 32) || p->sample_offset + p->n_samples < p->sample_offset)
+    return fail(h, TEPAI_ERANGE, "sample indices must stay below 2^32");
+  if (p->chi_max < 1 || p->chi_max > (uint32_t)kMaxChi) return fail(h, TEPAI_ERANGE, "chi_max must be in [1, 256]");
+  if (p->chi_per_sample)
+    for (uint64_t s = 0; s < p->n_samples; ++s)
+      if (p->chi_per_sample[s] < 1 || p->chi_per_sample[s] > p->chi_max)
+        return fail(h, TEPAI_ERANGE, "chi_per_sample entries must be in [1, chi_max]");
+  if (!std::isfinite(p->svd_cutoff) || p->svd_cutoff < 0.0) return fail(h, TEPAI_ERANGE, "svd_cutoff must be finite and >= 0");
+  if (!p->initial_bits) return fail(h, TEPAI_EINVAL, "initial_bits is NULL");
+  for (uint32_t i = 0; i < n; ++i)
+    if (p->initial_bits[i] > 1) return fail(h, TEPAI_EINVAL, "initial_bits entries must be 0 or 1");
+  if (p->n_obs > 256) return fail(h, TEPAI_ERANGE, "at most 256 observables");
+  if (p->n_strings && !p->strings) return fail(h, TEPAI_EINVAL, "strings is NULL");
+  for (uint32_t s = 0; s < p->n_strings; ++s) {
+    const tepai_pauli_string& ps = p->strings[s];
+    if (ps.n_ops < 1 || ps.n_ops > (uint32_t)kMaxStringOps) return fail(h, TEPAI_ERANGE, "Pauli strings hold 1..8 factors");
+    if (ps.observable >= p->n_obs) return fail(h, TEPAI_EINVAL, "string observable index out of range");
+    if (!ps.qubits || !ps.paulis) return fail(h, TEPAI_EINVAL, "string qubits/paulis NULL");
+    for (uint32_t i = 0; i < ps.n_ops; ++i) {
+      if (ps.qubits[i] >= n) return fail(h, TEPAI_EINVAL, "string qubit out of range");
+      if (ps.paulis[i] < 1 || ps.paulis[i] > 3) return fail(h, TEPAI_EINVAL, "string Pauli code must be X, Y or Z");
+      for (uint32_t j = 0; j < i; ++j)
+        if (ps.qubits[j] == ps.qubits[i]) return fail(h, TEPAI_EINVAL, "string qubits must be distinct");
+    }
+    if (!std::isfinite(ps.coeff)) return fail(h, TEPAI_ERANGE, "non-finite string coefficient");
+  }
+  if (p->precision != TEPAI_FP64) return fail(h, TEPAI_EINVAL, "unsupported precision");
+  if (p->flags != 0) return fail(h, TEPAI_EINVAL, "unsupported flags");
+  return TEPAI_OK;
+}
+
+// ------------------------------------------------------- workspace layout
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t rows, strings, bits, caps, states, tensors, work, total;
+  uint64_t site_stride, work_stride;
+};
+
+Layout layout(const tepai_problem& p, uint32_t l_eff, uint32_t count) {
+  Layout L{};
+  const uint64_t chi = p.chi_max;
+  L.site_stride = 2 * chi * chi;
+  L.work_stride = 3 * (2 * chi) * (2 * chi);
+  size_t off = 0;
+  L.rows = off;
+  off = align256(off + sizeof(DevRow) * l_eff);
+  L.strings = off;
+  off = align256(off + sizeof(DevString) * std::max<uint32_t>(p.n_strings, 1));
+  L.bits = off;
+  off = align256(off + p.n_qubits);
+  L.caps = off;
+  off = align256(off + sizeof(uint32_t) * count);
+  L.states = off;
+  off = align256(off + sizeof(SampleState) * count);
+  L.tensors = off;
+  off = align256(off + sizeof(double2) * L.site_stride * p.n_qubits * count);
+  L.work = off;
+  off = align256(off + sizeof(double2) * L.work_stride * count);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+}  // namespace tepai
+
+using namespace tepai;
+
+struct tepai_batch {
+  tepai_handle* h;
+  hipStream_t stream;
+  EngineArgs args;
+  uint32_t trotter_steps;
+  uint32_t layers_done;
+  uint32_t n_obs;
+  // host staging kept alive until destroy (async uploads)
+  std::vector<DevRow> rows;
+  std::vector<DevString> strings;
+  std::vector<uint8_t> bits;
+  std::vector<uint32_t> caps;
+};
+
+extern "C" {
+
+tepai_status tepai_create(tepai_handle** out, int device) {
+  if (!out) return TEPAI_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return TEPAI_EDEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return TEPAI_EDEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TEPAI_EDEVICE;
+  auto* h = new tepai_handle;
+  h->device = device;
+  *out = h;
+  return TEPAI_OK;
+}
+
+void tepai_destroy(tepai_handle* h) { delete h; }
+
+const char* tepai_last_error(const tepai_handle* h) { return h ? h->err.c_str() : "no handle"; }
+
+tepai_status tepai_validate(tepai_handle* h, const tepai_problem* p) {
+  if (h) h->err.clear();
+  return validate(h, p);
+}
+
+tepai_status tepai_pai_table(tepai_handle* h, const tepai_problem* p, uint32_t capacity,
+                             uint32_t* l_eff, uint32_t* term, double* theta, double* gamma,
+                             uint64_t* thresholds, double* log_g1_step, uint32_t* n_split_terms) {
+  tepai_status st = validate(h, p);
+  if (st != TEPAI_OK) return st;
+  if (!l_eff) return fail(h, TEPAI_EINVAL, "l_eff is NULL");
+  const Table t = build_table(*p);
+  *l_eff = (uint32_t)t.rows.size();
+  if (log_g1_step) *log_g1_step = t.log_step;
+  if (n_split_terms) *n_split_terms = t.n_split;
+  if (t.rows.size() > capacity) return fail(h, TEPAI_ENOMEM, "table capacity too small");
+  for (size_t i = 0; i < t.rows.size(); ++i) {
+    if (term) term[i] = t.rows[i].term;
+    if (theta) theta[i] = t.rows[i].theta;
+    if (gamma) std::memcpy(gamma + 3 * i, t.rows[i].g, 3 * sizeof(double));
+    if (thresholds) {
+      thresholds[2 * i] = t.rows[i].t1;
+      thresholds[2 * i + 1] = t.rows[i].t2;
+    }
+  }
+  return TEPAI_OK;
+}
+
+tepai_status tepai_sample_circuits(tepai_handle* h, const tepai_problem* p, uint64_t first,
+                                   uint64_t count, uint32_t layers, uint64_t capacity,
+                                   uint64_t* offsets, uint32_t* words, int8_t* signs) {
+  if (!h) return TEPAI_EINVAL;
+  tepai_status st = validate(h, p);
+  if (st != TEPAI_OK) return st;
+  if (!offsets || !signs) return fail(h, TEPAI_EINVAL, "offsets/signs NULL");
+  if (count == 0) {
+    offsets[0] = 0;
+    return TEPAI_OK;
+  }
+  if (first + count > p->n_samples) return fail(h, TEPAI_ERANGE, "samples beyond n_samples");
+  if (count > (1u << 30)) return fail(h, TEPAI_ERANGE, "count too large");
+  const Table t = build_table(*p);
+  const uint32_t L = (uint32_t)t.rows.size();
+  const uint32_t J = layers ? layers : p->trotter_steps;
+  if (J > p->trotter_steps) return fail(h, TEPAI_ERANGE, "layers beyond trotter_steps");
+  const uint64_t n_draws = (uint64_t)J * L;
+  if (n_draws >= (1ull << 30)) return fail(h, TEPAI_ERANGE, "N * L_eff must be < 2^30 for gate words");
+  const std::vector<DevRow> rows = device_rows(*p, t);
+  TEPAI_HIP(h, hipSetDevice(h->device));
+  DevRow* d_rows = nullptr;
+  uint64_t* d_counts = nullptr;
+  int8_t* d_signs = nullptr;
+  TEPAI_HIP(h, hipMalloc(&d_rows, sizeof(DevRow) * L));
+  TEPAI_HIP(h, hipMalloc(&d_counts, sizeof(uint64_t) * (count + 1)));
+  TEPAI_HIP(h, hipMalloc(&d_signs, count));
+  TEPAI_HIP(h, hipMemcpy(d_rows, rows.data(), sizeof(DevRow) * L, hipMemcpyHostToDevice));
+  const uint64_t s0 = p->sample_offset + first;
+  TEPAI_HIP(h, launch_sample_count(d_rows, L, p->seed, s0, count, n_draws, d_counts, d_signs, 0));
+  std::vector<uint64_t> counts(count);
+  TEPAI_HIP(h, hipMemcpy(counts.data(), d_counts, sizeof(uint64_t) * count, hipMemcpyDeviceToHost));
+  TEPAI_HIP(h, hipMemcpy(signs, d_signs, count, hipMemcpyDeviceToHost));
+  offsets[0] = 0;
+  for (uint64_t i = 0; i < count; ++i) offsets[i + 1] = offsets[i] + counts[i];
+  tepai_status result = TEPAI_OK;
+  if (offsets[count] > capacity) {
+    result = fail(h, TEPAI_ENOMEM, "gate capacity too small");
+  } else if (offsets[count] > 0) {
+    if (!words) return fail(h, TEPAI_EINVAL, "words NULL");
+    uint32_t* d_words = nullptr;
+    TEPAI_HIP(h, hipMemcpy(d_counts, offsets, sizeof(uint64_t) * count, hipMemcpyHostToDevice));
+    TEPAI_HIP(h, hipMalloc(&d_words, sizeof(uint32_t) * offsets[count]));
+    TEPAI_HIP(h, launch_sample_write(d_rows, L, p->seed, s0, count, n_draws, d_counts, d_words, 0));
+    TEPAI_HIP(h, hipMemcpy(words, d_words, sizeof(uint32_t) * offsets[count], hipMemcpyDeviceToHost));
+    TEPAI_HIP(h, hipFree(d_words));
+  }
+  TEPAI_HIP(h, hipFree(d_rows));
+  TEPAI_HIP(h, hipFree(d_counts));
+  TEPAI_HIP(h, hipFree(d_signs));
+  return result;
+}
+
+tepai_status tepai_workspace_size(tepai_handle* h, const tepai_problem* p, uint32_t count,
+                                  size_t* bytes) {
+  tepai_status st = validate(h, p);
+  if (st != TEPAI_OK) return st;
+  if (!bytes) return fail(h, TEPAI_EINVAL, "bytes is NULL");
+  const Table t = build_table(*p);
+  *bytes = layout(*p, (uint32_t)t.rows.size(), count).total;
+  return TEPAI_OK;
+}
+
+tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_t first,
+                                uint32_t count, void* workspace, size_t ws_bytes,
+                                void* hip_stream, tepai_batch** out) {
+  if (!h || !out) return TEPAI_EINVAL;
+  *out = nullptr;
+  tepai_status st = validate(h, p);
+  if (st != TEPAI_OK) return st;
+  if (count == 0) return fail(h, TEPAI_ERANGE, "count must be >= 1");
+  if (first + count > p->n_samples) return fail(h, TEPAI_ERANGE, "batch beyond n_samples");
+  if (!workspace || ((uintptr_t)workspace & 255)) return fail(h, TEPAI_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+  const Table t = build_table(*p);
+  const uint32_t L = (uint32_t)t.rows.size();
+  if (L > (uint32_t)kMaxRows) return fail(h, TEPAI_ERANGE, "more than 4096 table rows per Trotter step");
+  const Layout lay = layout(*p, L, count);
+  if (ws_bytes < lay.total) return fail(h, TEPAI_ENOMEM, "workspace smaller than tepai_workspace_size");
+  TEPAI_HIP(h, hipSetDevice(h->device));
+  auto* b = new tepai_batch;
+  b->h = h;
+  b->stream = (hipStream_t)hip_stream;
+  b->trotter_steps = p->trotter_steps;
+  b->layers_done = 0;
+  b->n_obs = p->n_obs;
+  b->rows = device_rows(*p, t);
+  b->strings.resize(std::max<uint32_t>(p->n_strings, 1));
+  for (uint32_t s = 0; s < p->n_strings; ++s) {
+    DevString d{};
+    d.n_ops = p->strings[s].n_ops;
+    d.observable = p->strings[s].observable;
+    d.coeff = p->strings[s].coeff;
+    for (uint32_t i = 0; i < d.n_ops; ++i) {
+      d.q[i] = p->strings[s].qubits[i];
+      d.p[i] = p->strings[s].paulis[i];
+    }
+    b->strings[s] = d;
+  }
+  b->bits.assign(p->initial_bits, p->initial_bits + p->n_qubits);
+  b->caps.resize(count);
+  for (uint32_t i = 0; i < count; ++i)
+    b->caps[i] = p->chi_per_sample ? p->chi_per_sample[first + i] : p->chi_max;
+  char* ws = (char*)workspace;
+  EngineArgs& a = b->args;
+  a.rows = (const DevRow*)(ws + lay.rows);
+  a.strings = (const DevString*)(ws + lay.strings);
+  a.init_bits = (const uint8_t*)(ws + lay.bits);
+  a.chi_caps = (const uint32_t*)(ws + lay.caps);
+  a.states = (SampleState*)(ws + lay.states);
+  a.tensors = (double2*)(ws + lay.tensors);
+  a.work = (double2*)(ws + lay.work);
+  a.site_stride = lay.site_stride;
+  a.work_stride = lay.work_stride;
+  a.first_sample = p->sample_offset + first;
+  a.seed = p->seed;
+  a.cutoff = p->svd_cutoff;
+  a.log_g1_step = t.log_step;
+  a.l_eff = L;
+  a.n = p->n_qubits;
+  a.chi_max = p->chi_max;
+  a.count = count;
+  a.n_strings = p->n_strings;
+  a.n_obs = p->n_obs;
+  hipError_t e = hipMemcpyAsync(ws + lay.rows, b->rows.data(), sizeof(DevRow) * L, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + lay.strings, b->strings.data(), sizeof(DevString) * b->strings.size(), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + lay.bits, b->bits.data(), p->n_qubits, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + lay.caps, b->caps.data(), sizeof(uint32_t) * count, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = launch_init(a, b->stream);
+  if (e != hipSuccess) {
+    delete b;
+    return fail(h, TEPAI_EDEVICE, std::string("batch set-up: ") + hipGetErrorString(e));
+  }
+  *out = b;
+  return TEPAI_OK;
+}
+
+tepai_status tepai_batch_evolve(tepai_batch* b, uint32_t n_layers) {
+  if (!b) return TEPAI_EINVAL;
+  if (n_layers == 0) return TEPAI_OK;
+  if ((uint64_t)b->layers_done + n_layers > b->trotter_steps)
+    return fail(b->h, TEPAI_ERANGE, "evolve beyond the last Trotter step");
+  TEPAI_HIP(b->h, hipSetDevice(b->h->device));
+  TEPAI_HIP(b->h, launch_evolve(b->args, n_layers, b->stream));
+  b->layers_done += n_layers;
+  return TEPAI_OK;
+}
+
+tepai_status tepai_batch_observe(tepai_batch* b, double* d_values, double* d_weights) {
+  if (!b) return TEPAI_EINVAL;
+  if (!d_values || !d_weights) return fail(b->h, TEPAI_EINVAL, "output pointers NULL");
+  TEPAI_HIP(b->h, hipSetDevice(b->h->device));
+  TEPAI_HIP(b->h, launch_observe(b->args, d_values, d_weights, b->stream));
+  return TEPAI_OK;
+}
+
+tepai_status tepai_batch_stats(tepai_batch* b, tepai_sample_stats* out) {
+  if (!b || !out) return TEPAI_EINVAL;
+  TEPAI_HIP(b->h, hipSetDevice(b->h->device));
+  std::vector<SampleState> st(b->args.count);
+  TEPAI_HIP(b->h, hipMemcpyAsync(st.data(), b->args.states, sizeof(SampleState) * st.size(), hipMemcpyDeviceToHost, b->stream));
+  TEPAI_HIP(b->h, hipStreamSynchronize(b->stream));
+  for (size_t i = 0; i < st.size(); ++i) {
+    const SampleState& s = st[i];
+    tepai_sample_stats& o = out[i];
+    o.n_gates = s.n_gates;
+    o.updates = s.updates;
+    o.swap_updates = s.swap_updates;
+    o.shifts = s.shifts;
+    o.jacobi_sweeps = s.sweeps;
+    o.nonconverged = s.nonconverged;
+    o.ties = s.ties;
+    o.sum_chi3 = s.sum_chi3;
+    o.nominal_flops = s.nominal_flops;
+    o.discarded = s.discarded;
+    o.max_discarded = s.max_discarded;
+    o.min_gap = s.min_gap;
+    o.sign = s.sign;
+    o.layer = s.layer;
+    o.max_bond = s.max_bond;
+    o.flags = s.flags;
+  }
+  return TEPAI_OK;
+}
+
+void tepai_batch_destroy(tepai_batch* b) { delete b; }
+
+tepai_status tepai_reduce(tepai_handle* h, uint64_t count, uint32_t n_obs, const double* d_values,
+                          const double* d_weights, double* d_mean, double* d_std_err,
+                          void* hip_stream) {
+  if (!h) return TEPAI_EINVAL;
+  if (count == 0 || n_obs == 0) return fail(h, TEPAI_ERANGE, "count and n_obs must be >= 1");
+  if (!d_values || !d_weights || !d_mean || !d_std_err) return fail(h, TEPAI_EINVAL, "NULL pointer");
+  TEPAI_HIP(h, hipSetDevice(h->device));
+  TEPAI_HIP(h, launch_reduce(count, n_obs, d_values, d_weights, d_mean, d_std_err, (hipStream_t)hip_stream));
+  return TEPAI_OK;
+}
+
+tepai_status tepai_run(tepai_handle* h, const tepai_problem* p, uint32_t batch, double* mean,
+                       double* std_err, double* weights, double* values,
+                       tepai_sample_stats* stats) {
+  if (!h) return TEPAI_EINVAL;
+  tepai_status st = validate(h, p);
+  if (st != TEPAI_OK) return st;
+  if (!mean || !std_err || !weights) return fail(h, TEPAI_EINVAL, "output pointers NULL");
+  if (p->n_obs == 0) return fail(h, TEPAI_ERANGE, "n_obs must be >= 1");
+  TEPAI_HIP(h, hipSetDevice(h->device));
+  const uint64_t ns = p->n_samples;
+  size_t per1 = 0, per2 = 0;
+  if ((st = tepai_workspace_size(h, p, 1, &per1)) != TEPAI_OK) return st;
+  if ((st = tepai_workspace_size(h, p, 2, &per2)) != TEPAI_OK) return st;
+  const size_t per = per2 - per1;
+  size_t free_b = 0, total_b = 0;
+  TEPAI_HIP(h, hipMemGetInfo(&free_b, &total_b));
+  uint64_t B = batch ? batch : 1024;
+  B = std::min<uint64_t>(B, ns);
+  while (B > 1 && per1 + per * (B - 1) > free_b / 2) B /= 2;
+  size_t ws_bytes = 0;
+  if ((st = tepai_workspace_size(h, p, (uint32_t)B, &ws_bytes)) != TEPAI_OK) return st;
+  void* ws = nullptr;
+  double *d_v = nullptr, *d_w = nullptr, *d_m = nullptr, *d_se = nullptr;
+  TEPAI_HIP(h, hipMalloc(&ws, ws_bytes));
+  TEPAI_HIP(h, hipMalloc(&d_v, sizeof(double) * ns * p->n_obs));
+  TEPAI_HIP(h, hipMalloc(&d_w, sizeof(double) * ns));
+  TEPAI_HIP(h, hipMalloc(&d_m, sizeof(double) * p->n_obs));
+  TEPAI_HIP(h, hipMalloc(&d_se, sizeof(double) * p->n_obs));
+  std::vector<tepai_sample_stats> sbuf;
+  for (uint64_t first = 0; first < ns && st == TEPAI_OK; first += B) {
+    const uint32_t cnt = (uint32_t)std::min<uint64_t>(B, ns - first);
+    tepai_batch* b = nullptr;
+    st = tepai_batch_create(h, p, first, cnt, ws, ws_bytes, nullptr, &b);
+    if (st != TEPAI_OK) break;
+    // launches of at most 16 Trotter steps keep single kernels short
+    for (uint32_t done = 0; done < p->trotter_steps && st == TEPAI_OK;) {
+      const uint32_t step = std::min<uint32_t>(16, p->trotter_steps - done);
+      st = tepai_batch_evolve(b, step);
+      done += step;
+    }
+    if (st == TEPAI_OK) st = tepai_batch_observe(b, d_v + first * p->n_obs, d_w + first);
+    if (st == TEPAI_OK && stats) st = tepai_batch_stats(b, stats + first);
+    if (st == TEPAI_OK) {
+      hipError_t e = hipStreamSynchronize(nullptr);
+      if (e != hipSuccess) st = fail(h, TEPAI_EDEVICE, std::string("batch: ") + hipGetErrorString(e));
+    }
+    tepai_batch_destroy(b);
+  }
+  if (st == TEPAI_OK) st = tepai_reduce(h, ns, p->n_obs, d_v, d_w, d_m, d_se, nullptr);
+  if (st == TEPAI_OK) {
+    hipError_t e = hipMemcpy(mean, d_m, sizeof(double) * p->n_obs, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(std_err, d_se, sizeof(double) * p->n_obs, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(weights, d_w, sizeof(double) * ns, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && values) e = hipMemcpy(values, d_v, sizeof(double) * ns * p->n_obs, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) st = fail(h, TEPAI_EDEVICE, std::string("copy-out: ") + hipGetErrorString(e));
+  }
+  (void)hipFree(ws);
+  (void)hipFree(d_v);
+  (void)hipFree(d_w);
+  (void)hipFree(d_m);
+  (void)hipFree(d_se);
+  if (st == TEPAI_OK) {
+    for (uint32_t o = 0; o < p->n_obs; ++o)
+      if (!std::isfinite(mean[o])) return fail(h, TEPAI_ENUMERIC, "non-finite estimate");
+  }
+  return st;
+}
+
+}  // extern "C"

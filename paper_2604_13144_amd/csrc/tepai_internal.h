@@ -1,0 +1,86 @@
+// Internal layout shared by the host and device halves of libtepai.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "tepai.h"
+
+namespace tepai {
+
+constexpr int kMaxQubits = 256;
+constexpr int kMaxChi = 256;
+constexpr int kMaxRows = 4096;        // PAI table rows per Trotter step
+constexpr int kMaxStringOps = 8;
+constexpr int kThreads = 256;         // engine block: four wave64 wavefronts
+constexpr int kMaxSweeps = 60;        // Jacobi sweep cap per factorisation
+
+// One row of the PAI table: a (sub-)rotation of one Trotter step.
+struct DevRow {
+  uint64_t t1, t2;      // 63-bit thresholds: v < t1 -> A, v < t2 -> B, else C
+  double cb, sb;        // setting B = cb I - i sb P  (sb = sin(sign(theta) Delta / 2))
+  uint32_t nq;          // 1 or 2
+  uint32_t q0, q1;      // qubits (q1 unused when nq == 1)
+  uint32_t p0, p1;      // Pauli codes 1..3
+  uint32_t pad;
+};
+
+struct DevString {
+  uint32_t n_ops, observable;
+  uint32_t q[kMaxStringOps];
+  uint32_t p[kMaxStringOps];
+  double coeff;
+};
+
+// Per-sample state that persists between launches (one per batch slot).
+struct SampleState {
+  int32_t centre;
+  int32_t sign;
+  uint32_t layer;
+  uint32_t flags;
+  uint32_t chi_cap;
+  uint32_t max_bond;
+  uint64_t n_gates, updates, swap_updates, shifts, sweeps, nonconverged, ties;
+  double sum_chi3, nominal_flops, discarded, max_discarded, min_gap;
+  uint16_t bond[kMaxQubits + 1];   // bond[k] = dimension between sites k-1 and k
+};
+
+// Everything a kernel launch needs; passed by value.
+struct EngineArgs {
+  const DevRow* rows;
+  const DevString* strings;
+  const uint8_t* init_bits;
+  const uint32_t* chi_caps;   // [count] per-slot bond caps
+  SampleState* states;
+  double2* tensors;       // [count][n][site_stride]
+  double2* work;          // [count][work_stride]
+  uint64_t site_stride;   // complex elements per site slot: 2 chi_max^2
+  uint64_t work_stride;   // complex elements of scratch per sample
+  uint64_t first_sample;  // global index of slot 0
+  uint64_t seed;
+  double cutoff;
+  double log_g1_step;
+  uint32_t l_eff;
+  uint32_t n;
+  uint32_t chi_max;
+  uint32_t count;
+  uint32_t n_strings;
+  uint32_t n_obs;
+};
+
+// Kernel launchers (kernels.hip).
+hipError_t launch_init(const EngineArgs& a, hipStream_t s);
+hipError_t launch_evolve(const EngineArgs& a, uint32_t n_layers, hipStream_t s);
+hipError_t launch_observe(const EngineArgs& a, double* d_values, double* d_weights, hipStream_t s);
+hipError_t launch_reduce(uint64_t count, uint32_t n_obs, const double* v, const double* w,
+                         double* mean, double* se, hipStream_t s);
+hipError_t launch_sample_count(const DevRow* rows, uint32_t l_eff, uint64_t seed,
+                               uint64_t first_sample, uint64_t count, uint64_t n_draws,
+                               uint64_t* d_counts, int8_t* d_signs, hipStream_t s);
+hipError_t launch_sample_write(const DevRow* rows, uint32_t l_eff, uint64_t seed,
+                               uint64_t first_sample, uint64_t count, uint64_t n_draws,
+                               const uint64_t* d_offsets, uint32_t* d_words, hipStream_t s);
+
+}  // namespace tepai

@@ -1,0 +1,132 @@
+"""The C ABI of libtepai on the CPU: exports, struct layout, host logic.
+
+No compute call here touches a GPU: the PAI table, validation and workspace
+sizing are host code; everything on the device is tested under -m gpu.
+"""
+import ctypes as C
+import math
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import tepai_inputs as ti
+from oracle import pai
+from paper_2604_13144_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tepai.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tepai_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.PROTOTYPES)
+
+
+def test_struct_layout_matches_header():
+    probe = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "tepai.h"
+#define P(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+int main(void) {
+  printf("tepai_term %zu\n", sizeof(tepai_term));
+  printf("tepai_pauli_string %zu\n", sizeof(tepai_pauli_string));
+  printf("tepai_problem %zu\n", sizeof(tepai_problem));
+  printf("tepai_sample_stats %zu\n", sizeof(tepai_sample_stats));
+  P(tepai_term, coeff) P(tepai_problem, delta) P(tepai_problem, chi_per_sample)
+  P(tepai_problem, strings) P(tepai_problem, flags) P(tepai_sample_stats, sign)
+  P(tepai_sample_stats, flags) P(tepai_pauli_string, coeff)
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        cpath = os.path.join(d, "probe.c")
+        open(cpath, "w").write(probe)
+        exe = os.path.join(d, "probe")
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), cpath, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    got = dict(l.rsplit(" ", 1) for l in out.strip().splitlines())
+    ct = {"tepai_term": L.tepai_term, "tepai_pauli_string": L.tepai_pauli_string,
+          "tepai_problem": L.tepai_problem, "tepai_sample_stats": L.tepai_sample_stats}
+    for k, v in got.items():
+        if "." in k:
+            s, f = k.split(".")
+            assert getattr(ct[s], f).offset == int(v), k
+        else:
+            assert C.sizeof(ct[k]) == int(v), k
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+def test_host_table_equals_oracle_table(k):
+    p = ti.config(k)
+    t = L.tepai_pai_table(None, L.ProblemStruct(p))
+    o = pai.build_table(p)
+    assert t["l_eff"] == o.l_eff
+    assert t["n_split_terms"] == o.n_split_terms
+    assert np.array_equal(t["term"], [r.term for r in o.rows])
+    assert np.array_equal(t["theta"], [r.theta for r in o.rows])
+    assert np.max(np.abs(t["gamma"] - np.array([r.gamma for r in o.rows]))) <= 1e-15
+    thr = np.array([[r.t1, r.t2] for r in o.rows], dtype=np.uint64)
+    assert np.array_equal(t["thresholds"], thr)          # bit-exact sampler decisions
+    assert abs(t["log_g1_step"] - o.log_g1_step) <= 1e-14 * abs(o.log_g1_step)
+
+
+def bad(**kw):
+    return ti.config(1).with_(**kw)
+
+
+@pytest.mark.parametrize("problem,status", [
+    (bad(delta=math.pi), -2),
+    (bad(delta=0.0), -2),
+    (bad(trotter_steps=0), -2),
+    (bad(chi_max=0), -2),
+    (bad(chi_max=512), -2),
+    (bad(total_time=-1.0), -2),
+    (bad(svd_cutoff=-1e-3), -2),
+    (bad(terms=(ti.Term("XX", (0, 2), 1.0),)), -1),     # not ring neighbours
+    (bad(terms=(ti.Term("ZZ", (3, 3), 1.0),)), -1),
+    (bad(terms=(ti.Term("Z", (8,), 1.0),)), -1),
+    (bad(initial_bits="0101010"), None),                # handled by the binding
+    (bad(n_samples=0), -2),
+    (bad(sample_offset=2 ** 32 - 10), -2),
+])
+def test_validation_errors(problem, status):
+    if status is None:
+        with pytest.raises(Exception):
+            L.tepai_validate(None, L.ProblemStruct(problem))
+        return
+    with pytest.raises(L.TepaiError) as e:
+        L.tepai_validate(None, L.ProblemStruct(problem))
+    assert e.value.status == status
+
+
+def test_valid_configs_pass_and_wrap_bond_is_adjacent():
+    for k in range(1, 6):
+        L.tepai_validate(None, L.ProblemStruct(ti.config(k)))
+    # (n-1, 0) is a ring neighbour pair
+    L.tepai_validate(None, L.ProblemStruct(bad(terms=(ti.Term("XX", (7, 0), 1.0),))))
+
+
+def test_workspace_size_scales_with_batch():
+    ps = L.ProblemStruct(ti.config(4))
+    s1 = L.tepai_workspace_size(None, ps, 1)
+    s8 = L.tepai_workspace_size(None, ps, 8)
+    per = (s8 - s1) / 7
+    # per sample: n site slots of 2 chi^2 complex128 + 3 (2 chi)^2 scratch
+    chi, n = 128, 64
+    want = 16 * (n * 2 * chi * chi + 3 * (2 * chi) ** 2)
+    assert abs(per - want) / want < 0.01

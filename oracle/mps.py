@@ -105,10 +105,12 @@ class MPS:
         st.nominal_flops += nominal_update_flops(cl, cm, cr)
         st.discarded += disc
         st.max_discarded = max(st.max_discarded, disc)
-        if k < S.size and S[k] > 0:
+        if k < r:
+            # a cut made by the bond cap: the kept state is unique only when
+            # sigma_{k-1} > sigma_k; record the gap and flag near-ties
             gap = (S[k - 1] - S[k]) / S[0]
             st.min_gap = min(st.min_gap, gap)
-            if k < r and gap <= 1e-10:
+            if gap <= 1e-10:
                 st.ties += 1
         Sk = S[:k] / np.linalg.norm(S[:k])
         if right:

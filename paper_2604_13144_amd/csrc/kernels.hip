@@ -288,14 +288,11 @@ __device__ Factor factorise(double2* W, int R, int C, int cap, double cutoff, bo
       const double disc = tot > 0.0 ? (tot - kept) / tot : 0.0;
       sh.discarded += disc;
       if (disc > sh.max_disc) sh.max_disc = disc;
-      const int nsv = R < C ? R : C;
-      if (k < nsv) {
+      if (k < r) {   // a cut made by the bond cap
         const double sk = sh.sig2[sh.perm[k]];
-        if (sk > 0.0) {
-          const double gap = (sqrt(sh.sig2[sh.perm[k - 1]]) - sqrt(sk)) / sqrt(s0);
-          if (gap < sh.min_gap) sh.min_gap = gap;
-          if (k < r && gap <= 1e-10) sh.ties += 1;
-        }
+        const double gap = (sqrt(sh.sig2[sh.perm[k - 1]]) - sqrt(sk)) / sqrt(s0);
+        if (gap < sh.min_gap) sh.min_gap = gap;
+        if (gap <= 1e-10) sh.ties += 1;
       }
     }
   }

@@ -2,10 +2,12 @@
 
 Tolerance: 1e-10 per sample value in FP64, the bar the method's FP64 path is
 held to; weights must agree in sign exactly and in magnitude to 1e-14
-relative; gate counts, signs and the schedule's update/shift counts must be
-identical.  Truncated trajectories amplify rounding by ~1/gap at each
-truncation, so samples whose oracle trajectory passes a Schmidt gap below
-1e-7 (near-ties at the cut) are held to a looser 1e-7.
+relative; gate counts, signs and the schedule's update counts must be
+identical.  A truncation at the bond cap amplifies rounding by about
+1/gap, gap = (sigma_{k-1} - sigma_k) / sigma_0 at the cut, so a sample whose
+oracle trajectory has a smallest gap g < 1e-7 is held to 1e-17 / g instead,
+and a tie-flagged sample (g <= 1e-10: the truncated state is not unique) is
+excluded from the value check (its circuit, sign and weight still are).
 """
 import math
 
@@ -56,11 +58,17 @@ def compare(p, samples, vals, wts, st, first, layers=None, tol=TOL):
         assert int(st["updates"][i]) == r.stats.updates
         assert wts[i] * r.sign > 0
         assert abs(abs(wts[i]) - math.exp(lg)) <= 1e-14 * math.exp(lg)
+        if r.stats.ties:
+            assert int(st["ties"][i]) > 0 or st["min_gap"][i] < 1e-9
+            continue
         err = float(np.max(np.abs(vals[i] - r.values)))
         worst = max(worst, err)
-        lim = tol if r.stats.min_gap > 1e-7 else max(tol, 1e-7)
-        assert err <= lim, (s, err, r.stats.min_gap)
+        assert err <= value_tol(r, tol), (s, err, r.stats.min_gap)
     return worst
+
+
+def value_tol(r, tol=TOL):
+    return max(tol, 1e-17 / r.stats.min_gap)
 
 
 def test_cfg1_exact_regime(handle):
@@ -148,4 +156,5 @@ def test_heterogeneous_chi_per_sample(handle):
     t = pai.build_table(p)
     for i in range(6):
         r = run_sample(p, t, i)
-        assert np.max(np.abs(vals[i] - r.values)) <= (TOL if r.stats.min_gap > 1e-7 else 1e-7)
+        if not r.stats.ties:
+            assert np.max(np.abs(vals[i] - r.values)) <= value_tol(r)

@@ -6,11 +6,20 @@
 // key = seed), so no gate stream is ever materialised, and applies them to
 // the sample's MPS, which lives in HBM in the caller's workspace:
 //   site k of slot b: tensors + (b * n + k) * site_stride, layout A[a][s][c]
-//   (row-major, actual bond dimensions), complex128 as double2.
-// Every factorisation is a one-sided (Hestenes) Jacobi SVD done by the four
-// waves of the workgroup: columns are rotated pairwise in round-robin order,
-// one column pair per wave, with the wave's 64 lanes striding over the rows
-// and the pair held in registers between the dot products and the rotation.
+//   (row-major, actual bond dimensions), complex128 as z2.
+// Every factorisation is a one-sided (Hestenes) Jacobi SVD done by the eight
+// waves of the workgroup.  Each 16-lane row of a wave owns one column pair at
+// a time (E = 4 RPL matrix rows per lane), so the three inner products of a
+// pair are reduced with four DPP steps inside the row and a wave rotates four
+// pairs at once.  A sweep visits the columns, sorted by decreasing norm
+// (de Rijk's ordering), in blocks of JB: one block stays in registers (one
+// column per row) while every later block is staged through LDS and each of
+// its columns meets each register column once; the pairs inside a block are
+// then done in LDS.  Every column pair is rotated exactly once per sweep, as
+// in the cyclic method, while HBM sees each block only a few times per sweep.
+//
+// The engine is instantiated for RPL = 1, 2, 4, 8 (matrices of up to 64 RPL
+// rows, i.e. chi_max <= 32 RPL), which sizes registers and LDS blocks.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -23,23 +32,41 @@ namespace {
 
 constexpr int NT = kThreads;
 constexpr int NW = kThreads / 64;
-constexpr int kMaxRowsPerLane = (2 * kMaxChi + 63) / 64;   // rows of a column per lane
+constexpr int NROWS = NT / 16;    // 16-lane rows per block
+
+template <int RPL>
+struct JCfg {
+  static constexpr int E = 4 * RPL;                    // matrix rows per lane of a 16-lane row
+  static constexpr int JB = RPL <= 4 ? NROWS : NROWS / 2;   // columns per Jacobi block
+  static constexpr int LR = 16 * E + 1;                // LDS column stride (padded)
+};
 
 // ---------------------------------------------------------------- complex
-__device__ __forceinline__ double2 cmk(double r, double i) { return make_double2(r, i); }
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return cmk(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+// complex128 as a native two-lane vector (loads/stores of 16 bytes), with
+// pointer types that pin LDS (ds_*) and global (global_*) address spaces.
+typedef double z2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) z2 lz2;
+typedef __attribute__((address_space(1))) z2 gz2;
+
+__device__ __forceinline__ z2 cmk(double r, double i) {
+  z2 v;
+  v.x = r;
+  v.y = i;
+  return v;
+}
+__device__ __forceinline__ z2 cadd(z2 a, z2 b) { return cmk(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ z2 cmul(z2 a, z2 b) {
   return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ __forceinline__ double2 cconj(double2 a) { return cmk(a.x, -a.y); }
-__device__ __forceinline__ double2 cscale(double2 a, double s) { return cmk(a.x * s, a.y * s); }
+__device__ __forceinline__ z2 cconj(z2 a) { return cmk(a.x, -a.y); }
+__device__ __forceinline__ z2 cscale(z2 a, double s) { return cmk(a.x * s, a.y * s); }
 // acc += a * b
-__device__ __forceinline__ void cfma(double2& acc, double2 a, double2 b) {
+__device__ __forceinline__ void cfma(z2& acc, z2 a, z2 b) {
   acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
   acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
 }
 // acc += conj(a) * b
-__device__ __forceinline__ void cfmac(double2& acc, double2 a, double2 b) {
+__device__ __forceinline__ void cfmac(z2& acc, z2 a, z2 b) {
   acc.x = fma(a.x, b.x, fma(a.y, b.y, acc.x));
   acc.y = fma(a.x, b.y, fma(-a.y, b.x, acc.y));
 }
@@ -81,6 +108,29 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Move a double between lanes with a DPP control (both 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(h2, l2);
+}
+
+// Sum over the 16 lanes of each DPP row.  Every step adds the values of two
+// lanes that exchange with each other (xor 1, xor 2, mirror, half-mirror), so
+// both partners add the same two operands and all 16 lanes end with the
+// bitwise-identical sum (Q0 + Q3) + (Q1 + Q2) of the four quad sums; lanes
+// that later derive a rotation from these sums therefore all apply the same
+// rotation, even where the sign of |y|^2 - |x|^2 is decided by rounding.
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
+  v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
+  v += dpp_f64<0x140>(v);   // row_mirror: lane <-> 15 - lane (quad q <-> 3 - q)
+  v += dpp_f64<0x141>(v);   // row_half_mirror: quad 0 <-> 1, quad 2 <-> 3
+  return v;
+}
+
 // Fixed-order block sum (deterministic); all threads get the result.
 __device__ double block_sum(double v, double* red) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -96,7 +146,7 @@ __device__ double block_sum(double v, double* red) {
 
 // ---------------------------------------------------------------- Paulis
 // Element (r, c) of Pauli p (1 = X, 2 = Y, 3 = Z).
-__device__ __forceinline__ double2 pauli_el(uint32_t p, int r, int c) {
+__device__ __forceinline__ z2 pauli_el(uint32_t p, int r, int c) {
   if (p == 1) return cmk(r != c ? 1.0 : 0.0, 0.0);
   if (p == 2) return r == c ? cmk(0.0, 0.0) : cmk(0.0, r == 0 ? -1.0 : 1.0);
   if (p == 3) return cmk(r == c ? (r == 0 ? 1.0 : -1.0) : 0.0, 0.0);
@@ -105,12 +155,14 @@ __device__ __forceinline__ double2 pauli_el(uint32_t p, int r, int c) {
 
 // -------------------------------------------------------- shared memory
 struct Shared {
-  double2 pM[16];             // pending two-site operator, (qa, qb) order
-  double2 pLa[4], pLb[4];     // its local factors while it holds only C settings
-  double2 pPhase;
+  z2 G[16];              // operator of the two-site update in progress (site order)
+  z2 pM[16];             // pending two-site operator, (qa, qb) order
+  z2 pLa[4], pLb[4];     // its local factors while it holds only C settings
+  z2 pPhase;
   double sig2[2 * kMaxChi];   // squared column norms after Jacobi
   double red[NW * 4];
   uint16_t perm[2 * kMaxChi]; // columns by descending norm
+  uint16_t order[2 * kMaxChi];// Jacobi sweep order
   uint16_t bond[kMaxQubits + 1];
   uint16_t qubit_at[kMaxQubits];
   uint16_t site_of[kMaxQubits];
@@ -126,17 +178,18 @@ struct Shared {
 };
 
 struct Slot {
-  double2* T;      // site tensors of this sample
-  double2* Y0;     // scratch: factorised matrix (kept)
-  double2* W;      // scratch: Jacobi working copy
-  double2* P;      // scratch: projections
+  z2* T;      // site tensors of this sample
+  z2* Y0;     // scratch: factorised matrix (kept)
+  z2* W;      // scratch: Jacobi working copy
+  z2* P;      // scratch: projections
+  z2* Jl;     // LDS staging block of the Jacobi sweeps
   uint64_t ss;     // site stride
   double cutoff;
   uint32_t chi;
   uint32_t n;
 };
 
-__device__ __forceinline__ double2* site(const Slot& s, int k) { return s.T + (uint64_t)k * s.ss; }
+__device__ __forceinline__ z2* site(const Slot& s, int k) { return s.T + (uint64_t)k * s.ss; }
 
 __device__ double svd_flops(double m, double n) {
   if (m < n) {
@@ -165,73 +218,214 @@ __device__ __forceinline__ void rr_pair(int round, int k, int Cp, int& p, int& q
   }
 }
 
-// One-sided Jacobi on the columns of W (R x C, column-major): on return the
-// columns are mutually orthogonal (W <- W V).  Returns the number of sweeps,
-// or -1 when the sweep cap was reached.
-__device__ int jacobi(double2* W, int R, int C, Shared& sh) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (C < 2) return 0;
-  const int Cp = C + (C & 1);
-  // scale for "numerically zero" columns: sigma_j^2 < 1e-32 ||W||_F^2
-  double f = 0.0;
-  for (int i = threadIdx.x; i < R * C; i += NT) {
-    const double2 x = W[i];
-    f += x.x * x.x + x.y * x.y;
+// One Jacobi rotation per 16-lane row: the row's lanes hold E elements each
+// of the column x in registers (element e of lane l is matrix row l + 16 e)
+// and read the partner column y from LDS twice (inner products, then the
+// update), which keeps register use at one column per row.  Only the first
+// ea = ceil(R / 16) elements are touched (a wave-uniform bound); rows of the
+// last element beyond R hold zeros and stay zero.
+// gamma = x^H y, zeta = (|y|^2 - |x|^2) / (2 |gamma|),
+// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2), s = c t,
+// x <- c x - s e^{-i phi} y, y <- s e^{i phi} x + c y, e^{i phi} = gamma/|gamma|.
+// Rows that are inactive or already orthogonal to tolerance leave both
+// columns untouched.  Returns whether this row rotated.
+template <int E>
+__device__ __forceinline__ bool rotate_rows(z2 (&x)[E], lz2* y, int ea, int l16, bool active,
+                                            double tiny, double tol2) {
+  double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (e < ea) {
+      const z2 b = y[l16 + 16 * e];
+      al = fma(x[e].x, x[e].x, fma(x[e].y, x[e].y, al));
+      be = fma(b.x, b.x, fma(b.y, b.y, be));
+      gr = fma(x[e].x, b.x, fma(x[e].y, b.y, gr));
+      gi = fma(x[e].x, b.y, fma(-x[e].y, b.x, gi));
+    }
   }
-  const double fro2 = block_sum(f, sh.red);
-  const double tiny = 1e-32 * fro2;
+  al = row16_sum(al);
+  be = row16_sum(be);
+  gr = row16_sum(gr);
+  gi = row16_sum(gi);
+  const double g2 = gr * gr + gi * gi;
+  const bool rot = active && al > tiny && be > tiny && g2 > tol2 * al * be;
+  if (rot) {
+    const double ig = 1.0 / sqrt(g2);
+    const double zeta = (be - al) * 0.5 * ig;
+    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double c = 1.0 / sqrt(1.0 + t * t);
+    const double s = c * t;
+    const double er = gr * ig, ei = gi * ig;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (e < ea) {
+        const z2 a = x[e], b = y[l16 + 16 * e];
+        const z2 eb = cmk(er * b.x + ei * b.y, er * b.y - ei * b.x);   // e^{-i phi} y
+        const z2 ex = cmk(er * a.x - ei * a.y, er * a.y + ei * a.x);   // e^{i phi} x
+        x[e] = cmk(c * a.x - s * eb.x, c * a.y - s * eb.y);
+        y[l16 + 16 * e] = cmk(s * ex.x + c * b.x, s * ex.y + c * b.y);
+      }
+    }
+  }
+  return rot;
+}
+
+// Column <-> row registers.  From/to global memory only rows < R exist; the
+// register (and LDS) copies are zero-padded to a multiple of 16 rows.
+template <int E>
+__device__ __forceinline__ void row_load_g(z2 (&x)[E], const gz2* col, int R, int l16) {
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int r = l16 + 16 * e;
+    x[e] = r < R ? col[r] : cmk(0.0, 0.0);
+  }
+}
+
+template <int E>
+__device__ __forceinline__ void row_store_g(const z2 (&x)[E], gz2* col, int R, int l16) {
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int r = l16 + 16 * e;
+    if (r < R) col[r] = x[e];
+  }
+}
+
+template <int E>
+__device__ __forceinline__ void row_load_l(z2 (&x)[E], const lz2* col, int ea, int l16) {
+#pragma unroll
+  for (int e = 0; e < E; ++e) x[e] = e < ea ? col[l16 + 16 * e] : cmk(0.0, 0.0);
+}
+
+template <int E>
+__device__ __forceinline__ void row_store_l(const z2 (&x)[E], lz2* col, int ea, int l16) {
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    if (e < ea) col[l16 + 16 * e] = x[e];
+}
+
+template <int E>
+__device__ __forceinline__ double row_norm2(const z2 (&x)[E]) {
+  double a = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) a = fma(x[e].x, x[e].x, fma(x[e].y, x[e].y, a));
+  return row16_sum(a);
+}
+
+// One-sided Jacobi on the columns of W (R x C, column-major, R <= 64 RPL):
+// on return the columns are mutually orthogonal (W <- W V).  Jl_ is the LDS
+// staging block (JB columns).  Returns the number of sweeps, or -1 when the
+// sweep cap was reached.
+template <int RPL>
+__device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
+  using K = JCfg<RPL>;
+  constexpr int E = K::E, JB = K::JB, LR = K::LR;
+  gz2* W = (gz2*)W_;
+  lz2* Jl = (lz2*)Jl_;
+  const int l16 = threadIdx.x & 15, row = threadIdx.x >> 4;
+  const int ea = (R + 15) >> 4;
+  if (C < 2) return 0;
+  // column norms (also the first sweep's ordering) and ||W||_F^2
+#pragma unroll 1
+  for (int j = row; j < C; j += NROWS) {
+    z2 x[E];
+    row_load_g<E>(x, W + (uint64_t)j * R, R, l16);
+    const double a = row_norm2<E>(x);
+    if (l16 == 0) sh.sig2[j] = a;
+  }
+  __syncthreads();
+  double fro2 = 0.0;
+  for (int j = 0; j < C; ++j) fro2 += sh.sig2[j];
+  const double tiny = 1e-32 * fro2;     // sigma_j^2 below this is numerically zero
   const double tol = 1e-15 * sqrt((double)R);
+  const double tol2 = tol * tol;
+  const int nb = (C + JB - 1) / JB;
+#pragma unroll 1
   for (int sweep = 1; sweep <= kMaxSweeps; ++sweep) {
+    // order columns by decreasing norm (ties by index): de Rijk's ordering
+    for (int j = threadIdx.x; j < C; j += NT) {
+      const double v = sh.sig2[j];
+      int rank = 0;
+#pragma unroll 4
+      for (int i = 0; i < C; ++i) {
+        const double u = sh.sig2[i];
+        rank += (u > v) || (u == v && i < j);
+      }
+      sh.order[rank] = (uint16_t)j;
+    }
     if (threadIdx.x == 0) sh.flag = 0;
     __syncthreads();
-    for (int round = 0; round < Cp - 1; ++round) {
-      for (int k = wv; k < Cp / 2; k += NW) {
-        int p, q;
-        rr_pair(round, k, Cp, p, q);
-        if (q >= C) continue;
-        double2* wp = W + (uint64_t)p * R;
-        double2* wq = W + (uint64_t)q * R;
-        double2 xs[kMaxRowsPerLane], ys[kMaxRowsPerLane];
-        double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+    bool rot = false;
+#pragma unroll 1
+    for (int I = 0; I < nb; ++I) {
+      const int pi = I * JB + row;                       // position of this row's column
+      const bool ai = row < JB && pi < C;
+      const int ci = ai ? sh.order[pi] : 0;
+      z2 xi[E];
+      if (ai) {
+        row_load_g<E>(xi, W + (uint64_t)ci * R, R, l16);
+      } else {
 #pragma unroll
-        for (int t = 0; t < kMaxRowsPerLane; ++t) {
-          const int r = lane + 64 * t;
-          if (r < R) {
-            const double2 x = wp[r], y = wq[r];
-            xs[t] = x;
-            ys[t] = y;
-            al = fma(x.x, x.x, fma(x.y, x.y, al));
-            be = fma(y.x, y.x, fma(y.y, y.y, be));
-            gr = fma(x.x, y.x, fma(x.y, y.y, gr));
-            gi = fma(x.x, y.y, fma(-x.y, y.x, gi));
+        for (int e = 0; e < E; ++e) xi[e] = cmk(0.0, 0.0);
+      }
+#pragma unroll 1
+      for (int J = I + 1; J < nb; ++J) {
+        if (row < JB) {   // stage block J: one column per row
+          const int pj = J * JB + row;
+          z2 y[E];
+          if (pj < C) {
+            row_load_g<E>(y, W + (uint64_t)sh.order[pj] * R, R, l16);
+          } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) y[e] = cmk(0.0, 0.0);
+          }
+          row_store_l<E>(y, Jl + row * LR, ea, l16);
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int rr = 0; rr < JB; ++rr) {
+          const int jj = (row + rr) % JB;
+          const bool act = ai && J * JB + jj < C;
+          if (row < JB) rot |= rotate_rows<E>(xi, Jl + jj * LR, ea, l16, act, tiny, tol2);
+          __syncthreads();
+        }
+        if (row < JB && J * JB + row < C) {
+          z2 y[E];
+          row_load_l<E>(y, Jl + row * LR, ea, l16);
+          row_store_g<E>(y, W + (uint64_t)sh.order[J * JB + row] * R, R, l16);
+        }
+        __syncthreads();
+      }
+      // pairs inside block I, in LDS (round-robin over the JB columns)
+      if (row < JB) row_store_l<E>(xi, Jl + row * LR, ea, l16);
+      __syncthreads();
+#pragma unroll 1
+      for (int round = 0; round < JB - 1; ++round) {
+        const bool on = row < JB / 2;
+        if (on) {
+          int p, q;
+          rr_pair(round, row, JB, p, q);
+          const bool act = I * JB + q < C;
+          z2 x[E];
+          row_load_l<E>(x, Jl + p * LR, ea, l16);
+          if (rotate_rows<E>(x, Jl + q * LR, ea, l16, act, tiny, tol2)) {
+            row_store_l<E>(x, Jl + p * LR, ea, l16);
+            rot = true;
           }
         }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        gr = wave_sum(gr);
-        gi = wave_sum(gi);
-        const double g = sqrt(gr * gr + gi * gi);
-        if (al <= tiny || be <= tiny || !(g > tol * sqrt(al * be))) continue;
-        const double zeta = (be - al) / (2.0 * g);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        const double er = gr / g, ei = gi / g;   // e^{i phi} = gamma / |gamma|
-        // w_p <- c w_p - s e^{-i phi} w_q ;  w_q <- s e^{i phi} w_p + c w_q
-#pragma unroll
-        for (int t2 = 0; t2 < kMaxRowsPerLane; ++t2) {
-          const int r = lane + 64 * t2;
-          if (r < R) {
-            const double2 x = xs[t2], y = ys[t2];
-            const double2 ey = cmk(er * y.x + ei * y.y, er * y.y - ei * y.x);
-            const double2 ex = cmk(er * x.x - ei * x.y, er * x.y + ei * x.x);
-            wp[r] = cmk(c * x.x - s * ey.x, c * x.y - s * ey.y);
-            wq[r] = cmk(s * ex.x + c * y.x, s * ex.y + c * y.y);
-          }
-        }
-        if (lane == 0) sh.flag = 1;
+        __syncthreads();
+      }
+      // write block I back and record its final column norms for the next order
+      if (ai) {
+        z2 x[E];
+        row_load_l<E>(x, Jl + row * LR, ea, l16);
+        row_store_g<E>(x, W + (uint64_t)ci * R, R, l16);
+        const double a = row_norm2<E>(x);
+        if (l16 == 0) sh.sig2[ci] = a;
       }
       __syncthreads();
     }
+    if (rot) sh.flag = 1;
+    __syncthreads();
     const int rotated = sh.flag;
     __syncthreads();
     if (!rotated) return sweep;
@@ -246,12 +440,13 @@ struct Factor {
 
 // Jacobi SVD of W (R x C), sort, choose k = min(cap, #{sigma > cutoff sigma_0}),
 // record statistics.  sh.perm[j] is the column of the j-th largest sigma.
-__device__ Factor factorise(double2* W, int R, int C, int cap, double cutoff, bool record,
-                            Shared& sh) {
+template <int RPL>
+__device__ Factor factorise(z2* W, int R, int C, int cap, double cutoff, bool record,
+                            Shared& sh, z2* Jl) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int sweeps = jacobi(W, R, C, sh);
+  const int sweeps = jacobi<RPL>(W, R, C, sh, Jl);
   for (int j = wv; j < C; j += NW) {
-    const double2* w = W + (uint64_t)j * R;
+    const z2* w = W + (uint64_t)j * R;
     double a = 0.0;
     for (int r = lane; r < R; r += 64) a = fma(w[r].x, w[r].x, fma(w[r].y, w[r].y, a));
     a = wave_sum(a);
@@ -305,14 +500,14 @@ __device__ Factor factorise(double2* W, int R, int C, int cap, double cutoff, bo
 
 // P[j][col] = sum_r conj(yhat_j[r]) Y0[col*R + r] for j < k, where yhat_j is
 // column perm[j] of W normalised to unit length.
-__device__ void project(const double2* W, const double2* Y0, double2* P, int R, int C, int k,
+__device__ void project(const z2* W, const z2* Y0, z2* P, int R, int C, int k,
                         Shared& sh) {
   for (int idx = threadIdx.x; idx < k * C; idx += NT) {
     const int j = idx / C, col = idx - j * C;
     const int pj = sh.perm[j];
-    const double2* w = W + (uint64_t)pj * R;
-    const double2* y = Y0 + (uint64_t)col * R;
-    double2 acc = cmk(0.0, 0.0);
+    const z2* w = W + (uint64_t)pj * R;
+    const z2* y = Y0 + (uint64_t)col * R;
+    z2 acc = cmk(0.0, 0.0);
     for (int r = 0; r < R; ++r) cfmac(acc, w[r], y[r]);
     P[idx] = cscale(acc, 1.0 / sqrt(sh.sig2[pj]));
   }
@@ -320,15 +515,15 @@ __device__ void project(const double2* W, const double2* Y0, double2* P, int R, 
 }
 
 // -------------------------------------------------------- MPS operations
-__device__ void apply_local(const Slot& S, int k, const double2 U[4], Shared& sh) {
-  double2* A = site(S, k);
+__device__ void apply_local(const Slot& S, int k, const z2 U[4], Shared& sh) {
+  z2* A = site(S, k);
   const int cl = sh.bond[k], cr = sh.bond[k + 1];
   for (int idx = threadIdx.x; idx < cl * cr; idx += NT) {
     const int a = idx / cr, b = idx - a * cr;
-    double2* x0 = A + (uint64_t)(a * 2 + 0) * cr + b;
-    double2* x1 = A + (uint64_t)(a * 2 + 1) * cr + b;
-    const double2 v0 = *x0, v1 = *x1;
-    double2 o0 = cmk(0.0, 0.0), o1 = cmk(0.0, 0.0);
+    z2* x0 = A + (uint64_t)(a * 2 + 0) * cr + b;
+    z2* x1 = A + (uint64_t)(a * 2 + 1) * cr + b;
+    const z2 v0 = *x0, v1 = *x1;
+    z2 o0 = cmk(0.0, 0.0), o1 = cmk(0.0, 0.0);
     cfma(o0, U[0], v0);
     cfma(o0, U[1], v1);
     cfma(o1, U[2], v0);
@@ -340,19 +535,20 @@ __device__ void apply_local(const Slot& S, int k, const double2 U[4], Shared& sh
 }
 
 // Move the centre from site c to c+1 (SVD of A_c as a (2 cl) x cr matrix).
+template <int RPL>
 __device__ void shift_right(const Slot& S, int c, double cutoff, Shared& sh) {
-  double2* A = site(S, c);
-  double2* B = site(S, c + 1);
+  z2* A = site(S, c);
+  z2* B = site(S, c + 1);
   const int cl = sh.bond[c], cr = sh.bond[c + 1], cr2 = sh.bond[c + 2];
   const int R = 2 * cl, C = cr;
   for (int idx = threadIdx.x; idx < R * C; idx += NT) {
     const int row = idx / C, col = idx - row * C;
-    const double2 v = A[idx];
+    const z2 v = A[idx];
     S.Y0[(uint64_t)col * R + row] = v;
     S.W[(uint64_t)col * R + row] = v;
   }
   __syncthreads();
-  const Factor f = factorise(S.W, R, C, C, cutoff, false, sh);
+  const Factor f = factorise<RPL>(S.W, R, C, C, cutoff, false, sh, S.Jl);
   const int k = f.k;
   project(S.W, S.Y0, S.P, R, C, k, sh);
   for (int idx = threadIdx.x; idx < R * k; idx += NT) {
@@ -365,7 +561,7 @@ __device__ void shift_right(const Slot& S, int c, double cutoff, Shared& sh) {
   const int nb = 2 * cr2;
   for (int idx = threadIdx.x; idx < k * nb; idx += NT) {
     const int j = idx / nb, col = idx - j * nb;
-    double2 acc = cmk(0.0, 0.0);
+    z2 acc = cmk(0.0, 0.0);
     for (int b = 0; b < cr; ++b) cfma(acc, S.P[j * C + b], B[(uint64_t)b * nb + col]);
     S.W[idx] = acc;
   }
@@ -380,18 +576,19 @@ __device__ void shift_right(const Slot& S, int c, double cutoff, Shared& sh) {
 }
 
 // Move the centre from site c to c-1 (SVD of A_c as a cl x (2 cr) matrix).
+template <int RPL>
 __device__ void shift_left(const Slot& S, int c, double cutoff, Shared& sh) {
-  double2* A = site(S, c);
-  double2* B = site(S, c - 1);
+  z2* A = site(S, c);
+  z2* B = site(S, c - 1);
   const int cl = sh.bond[c], cr = sh.bond[c + 1], cl0 = sh.bond[c - 1];
   const int R = 2 * cr, C = cl;
   for (int idx = threadIdx.x; idx < R * C; idx += NT) {
-    const double2 v = cconj(A[idx]);      // Y = A^H, same memory order
+    const z2 v = cconj(A[idx]);      // Y = A^H, same memory order
     S.Y0[idx] = v;
     S.W[idx] = v;
   }
   __syncthreads();
-  const Factor f = factorise(S.W, R, C, C, cutoff, false, sh);
+  const Factor f = factorise<RPL>(S.W, R, C, C, cutoff, false, sh, S.Jl);
   const int k = f.k;
   project(S.W, S.Y0, S.P, R, C, k, sh);
   for (int idx = threadIdx.x; idx < k * R; idx += NT) {
@@ -404,7 +601,7 @@ __device__ void shift_left(const Slot& S, int c, double cutoff, Shared& sh) {
   const int nrow = 2 * cl0;
   for (int idx = threadIdx.x; idx < nrow * k; idx += NT) {
     const int xs = idx / k, j = idx - xs * k;
-    double2 acc = cmk(0.0, 0.0);
+    z2 acc = cmk(0.0, 0.0);
     for (int a = 0; a < cl; ++a) cfma(acc, B[(uint64_t)xs * cl + a], cconj(S.P[j * C + a]));
     S.W[idx] = acc;
   }
@@ -418,46 +615,45 @@ __device__ void shift_left(const Slot& S, int c, double cutoff, Shared& sh) {
   __syncthreads();
 }
 
+template <int RPL>
 __device__ void move_centre_to(const Slot& S, int i, Shared& sh) {
-  while (sh.centre < i) shift_right(S, sh.centre, S.cutoff, sh);
-  while (sh.centre > i + 1) shift_left(S, sh.centre, S.cutoff, sh);
+  while (sh.centre < i) shift_right<RPL>(S, sh.centre, S.cutoff, sh);
+  while (sh.centre > i + 1) shift_left<RPL>(S, sh.centre, S.cutoff, sh);
 }
 
 // Truncated two-site update of sites (i, i+1) with operator G (site order,
 // index s_i * 2 + s_{i+1}).  right: centre ends on i+1, else on i.
-__device__ void two_site(const Slot& S, int i, const double2* G, bool right, bool is_swap,
-                         Shared& sh) {
-  move_centre_to(S, i, sh);
-  double2* A = site(S, i);
-  double2* B = site(S, i + 1);
+template <int RPL>
+__device__ void two_site(const Slot& S, int i, bool right, bool is_swap, Shared& sh) {
+  move_centre_to<RPL>(S, i, sh);
+  const z2* G = sh.G;
+  z2* A = site(S, i);
+  z2* B = site(S, i + 1);
   const int cl = sh.bond[i], cm = sh.bond[i + 1], cr = sh.bond[i + 2];
   const int M = 2 * cl, N = 2 * cr;
   const int R = right ? M : N, C = right ? N : M;
   // theta'[(a,u),(v,c)] = sum_{s,t} G[uv][st] sum_b A[a,s,b] B[b,t,c]
-  double2 g[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) g[e] = G[e];
   for (int idx = threadIdx.x; idx < cl * cr; idx += NT) {
     const int a = idx / cr, c = idx - a * cr;
-    double2 t00 = cmk(0, 0), t01 = cmk(0, 0), t10 = cmk(0, 0), t11 = cmk(0, 0);
-    const double2* a0 = A + (uint64_t)(a * 2 + 0) * cm;
-    const double2* a1 = A + (uint64_t)(a * 2 + 1) * cm;
+    z2 t00 = cmk(0, 0), t01 = cmk(0, 0), t10 = cmk(0, 0), t11 = cmk(0, 0);
+    const z2* a0 = A + (uint64_t)(a * 2 + 0) * cm;
+    const z2* a1 = A + (uint64_t)(a * 2 + 1) * cm;
     for (int b = 0; b < cm; ++b) {
-      const double2 x0 = a0[b], x1 = a1[b];
-      const double2 y0 = B[(uint64_t)(b * 2 + 0) * cr + c], y1 = B[(uint64_t)(b * 2 + 1) * cr + c];
+      const z2 x0 = a0[b], x1 = a1[b];
+      const z2 y0 = B[(uint64_t)(b * 2 + 0) * cr + c], y1 = B[(uint64_t)(b * 2 + 1) * cr + c];
       cfma(t00, x0, y0);
       cfma(t01, x0, y1);
       cfma(t10, x1, y0);
       cfma(t11, x1, y1);
     }
-    const double2 tv[4] = {t00, t01, t10, t11};
+    const z2 tv[4] = {t00, t01, t10, t11};
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
-        double2 o = cmk(0, 0);
+        z2 o = cmk(0, 0);
 #pragma unroll
-        for (int st = 0; st < 4; ++st) cfma(o, g[(u * 2 + v) * 4 + st], tv[st]);
+        for (int st = 0; st < 4; ++st) cfma(o, G[(u * 2 + v) * 4 + st], tv[st]);
         const int row = a * 2 + u, col = v * cr + c;
         uint64_t at;
         if (right) {
@@ -472,7 +668,7 @@ __device__ void two_site(const Slot& S, int i, const double2* G, bool right, boo
     }
   }
   __syncthreads();
-  const Factor f = factorise(S.W, R, C, (int)S.chi, S.cutoff, true, sh);
+  const Factor f = factorise<RPL>(S.W, R, C, (int)S.chi, S.cutoff, true, sh, S.Jl);
   const int k = f.k;
   project(S.W, S.Y0, S.P, R, C, k, sh);
   if (right) {
@@ -508,15 +704,16 @@ __device__ void two_site(const Slot& S, int i, const double2* G, bool right, boo
   __syncthreads();
 }
 
+template <int RPL>
 __device__ void swap_sites(const Slot& S, int i, bool right, Shared& sh) {
-  double2 G[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) G[e] = cmk(0, 0);
-  G[0 * 4 + 0] = cmk(1, 0);
-  G[1 * 4 + 2] = cmk(1, 0);
-  G[2 * 4 + 1] = cmk(1, 0);
-  G[3 * 4 + 3] = cmk(1, 0);
-  two_site(S, i, G, right, true, sh);
+  if (threadIdx.x < 16) {
+    const int r = threadIdx.x >> 2, c = threadIdx.x & 3;
+    // SWAP |s_i s_{i+1}> = |s_{i+1} s_i>
+    const int sw = ((c & 1) << 1) | (c >> 1);
+    sh.G[threadIdx.x] = cmk(r == sw ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  two_site<RPL>(S, i, right, true, sh);
   if (threadIdx.x == 0) {
     const int a = sh.qubit_at[i], b = sh.qubit_at[i + 1];
     sh.qubit_at[i] = (uint16_t)b;
@@ -528,11 +725,12 @@ __device__ void swap_sites(const Slot& S, int i, bool right, Shared& sh) {
 }
 
 // Apply the pending same-pair run (if any) and clear it.
+template <int RPL>
 __device__ void flush(const Slot& S, Shared& sh) {
   if (!sh.p_active) return;
   const int qa = sh.p_qa, qb = sh.p_qb;
   if (!sh.p_has) {
-    double2 Ua[4], Ub[4];
+    z2 Ua[4], Ub[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       Ua[e] = cmul(sh.pPhase, sh.pLa[e]);
@@ -543,40 +741,38 @@ __device__ void flush(const Slot& S, Shared& sh) {
   } else {
     int ia = sh.site_of[qa], ib = sh.site_of[qb];
     const int lo = ia < ib ? ia : ib, hi = ia < ib ? ib : ia;
-    for (int s = hi - 1; s > lo; --s) swap_sites(S, s, false, sh);
+    for (int s = hi - 1; s > lo; --s) swap_sites<RPL>(S, s, false, sh);
     ia = sh.site_of[qa];
     ib = sh.site_of[qb];
-    double2 G[16];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        // exchange tensor factors when qa sits on the right site
-        const int rr = ia < ib ? r : ((r & 1) << 1 | (r >> 1));
-        const int cc = ia < ib ? c : ((c & 1) << 1 | (c >> 1));
-        G[r * 4 + c] = sh.pM[rr * 4 + cc];
-      }
+    if (threadIdx.x < 16) {
+      const int r = threadIdx.x >> 2, c = threadIdx.x & 3;
+      // exchange tensor factors when qa sits on the right site
+      const int rr = ia < ib ? r : ((r & 1) << 1 | (r >> 1));
+      const int cc = ia < ib ? c : ((c & 1) << 1 | (c >> 1));
+      sh.G[threadIdx.x] = sh.pM[rr * 4 + cc];
     }
-    two_site(S, lo, G, true, false, sh);
-    for (int s = lo + 1; s < hi; ++s) swap_sites(S, s, true, sh);
+    __syncthreads();
+    two_site<RPL>(S, lo, true, false, sh);
+    for (int s = lo + 1; s < hi; ++s) swap_sites<RPL>(S, s, true, sh);
   }
   if (threadIdx.x == 0) sh.p_active = 0;
   __syncthreads();
 }
 
 // Process one sampled non-identity gate (setting 1 = B, 2 = C) of row r.
+template <int RPL>
 __device__ void process_gate(const Slot& S, const DevRow& row, int setting, int layer_unused,
                              Shared& sh) {
   (void)layer_unused;
   if (row.nq == 1) {
     const int q = row.q0;
-    if (sh.p_active && (q == sh.p_qa || q == sh.p_qb)) flush(S, sh);
-    double2 U[4];
+    if (sh.p_active && (q == sh.p_qa || q == sh.p_qb)) flush<RPL>(S, sh);
+    z2 U[4];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        const double2 P = pauli_el(row.p0, r, c);
+        const z2 P = pauli_el(row.p0, r, c);
         // B: cb I - i sb P ;  C: -i P
         const double cb = setting == 1 ? row.cb : 0.0, sb = setting == 1 ? row.sb : 1.0;
         U[r * 2 + c] = cmk((r == c ? cb : 0.0) + sb * P.y, -sb * P.x);
@@ -587,7 +783,7 @@ __device__ void process_gate(const Slot& S, const DevRow& row, int setting, int 
   }
   const int qa = row.q0, qb = row.q1;
   if (sh.p_active && !((qa == sh.p_qa && qb == sh.p_qb) || (qa == sh.p_qb && qb == sh.p_qa)))
-    flush(S, sh);
+    flush<RPL>(S, sh);
   if (threadIdx.x == 0) {
     if (!sh.p_active) {
       sh.p_active = 1;
@@ -605,17 +801,17 @@ __device__ void process_gate(const Slot& S, const DevRow& row, int setting, int 
     const bool same = (qa == sh.p_qa);
     const uint32_t pa = same ? row.p0 : row.p1, pb = same ? row.p1 : row.p0;
     const double cb = setting == 1 ? row.cb : 0.0, sb = setting == 1 ? row.sb : 1.0;
-    double2 G[16];
+    z2 G[16];
     for (int r = 0; r < 4; ++r) {
       for (int c = 0; c < 4; ++c) {
-        const double2 P = cmul(pauli_el(pa, r >> 1, c >> 1), pauli_el(pb, r & 1, c & 1));
+        const z2 P = cmul(pauli_el(pa, r >> 1, c >> 1), pauli_el(pb, r & 1, c & 1));
         G[r * 4 + c] = cmk((r == c ? cb : 0.0) + sb * P.y, -sb * P.x);
       }
     }
-    double2 Mn[16];
+    z2 Mn[16];
     for (int r = 0; r < 4; ++r) {
       for (int c = 0; c < 4; ++c) {
-        double2 acc = cmk(0, 0);
+        z2 acc = cmk(0, 0);
         for (int m = 0; m < 4; ++m) cfma(acc, G[r * 4 + m], sh.pM[m * 4 + c]);
         Mn[r * 4 + c] = acc;
       }
@@ -624,10 +820,10 @@ __device__ void process_gate(const Slot& S, const DevRow& row, int setting, int 
     if (setting == 1) {
       sh.p_has = 1;
     } else {
-      double2 La[4], Lb[4];
+      z2 La[4], Lb[4];
       for (int r = 0; r < 2; ++r) {
         for (int c = 0; c < 2; ++c) {
-          double2 a = cmk(0, 0), b = cmk(0, 0);
+          z2 a = cmk(0, 0), b = cmk(0, 0);
           for (int m = 0; m < 2; ++m) {
             cfma(a, pauli_el(pa, r, m), sh.pLa[m * 2 + c]);
             cfma(b, pauli_el(pb, r, m), sh.pLb[m * 2 + c]);
@@ -697,12 +893,13 @@ __device__ void store_state(const EngineArgs& a, int slot, Shared& sh, uint32_t 
   }
 }
 
-__device__ Slot make_slot(const EngineArgs& a, int slot) {
+__device__ Slot make_slot(const EngineArgs& a, int slot, z2* Jl) {
   Slot S;
+  S.Jl = Jl;
   S.ss = a.site_stride;
-  S.T = a.tensors + (uint64_t)slot * a.n * a.site_stride;
+  S.T = reinterpret_cast<z2*>(a.tensors) + (uint64_t)slot * a.n * a.site_stride;
   const uint64_t q = a.work_stride / 3;
-  S.Y0 = a.work + (uint64_t)slot * a.work_stride;
+  S.Y0 = reinterpret_cast<z2*>(a.work) + (uint64_t)slot * a.work_stride;
   S.W = S.Y0 + q;
   S.P = S.W + q;
   S.cutoff = a.cutoff;
@@ -715,7 +912,7 @@ __device__ Slot make_slot(const EngineArgs& a, int slot) {
 __global__ __launch_bounds__(NT) void init_kernel(EngineArgs a) {
   const int slot = blockIdx.x;
   SampleState* st = a.states + slot;
-  double2* T = a.tensors + (uint64_t)slot * a.n * a.site_stride;
+  z2* T = reinterpret_cast<z2*>(a.tensors) + (uint64_t)slot * a.n * a.site_stride;
   for (int k = threadIdx.x; k < (int)a.n; k += NT) {
     const int bit = a.init_bits[k] ? 1 : 0;
     T[(uint64_t)k * a.site_stride + 0] = cmk(bit ? 0.0 : 1.0, 0.0);
@@ -736,10 +933,12 @@ __global__ __launch_bounds__(NT) void init_kernel(EngineArgs a) {
   }
 }
 
+template <int RPL>
 __global__ __launch_bounds__(NT) void evolve_kernel(EngineArgs a, uint32_t n_layers) {
   __shared__ Shared sh;
+  __shared__ z2 Jl[JCfg<RPL>::JB * JCfg<RPL>::LR];
   const int slot = blockIdx.x;
-  const Slot S = make_slot(a, slot);
+  const Slot S = make_slot(a, slot, Jl);
   load_state(a, slot, sh);
   const uint32_t sample = (uint32_t)(a.first_sample + slot);
   const uint32_t L = a.l_eff;
@@ -763,9 +962,9 @@ __global__ __launch_bounds__(NT) void evolve_kernel(EngineArgs a, uint32_t n_lay
     for (uint32_t r = 0; r < L; ++r) {
       const int c = sh.choice[r];
       if (c == 0) continue;
-      process_gate(S, a.rows[r], c, (int)layer, sh);
+      process_gate<RPL>(S, a.rows[r], c, (int)layer, sh);
     }
-    flush(S, sh);     // runs end at Trotter-step boundaries
+    flush<RPL>(S, sh);     // runs end at Trotter-step boundaries
     __syncthreads();  // every thread is done reading this step's settings
   }
   store_state(a, slot, sh, layer0 + n_layers);
@@ -775,20 +974,22 @@ __global__ __launch_bounds__(NT) void evolve_kernel(EngineArgs a, uint32_t n_lay
 // evaluate every Pauli string whose first site is c by a transfer-matrix
 // contraction from c (left part left-canonical) to its last site (right part
 // right-canonical), normalised by the centre's squared norm.
+template <int RPL>
 __global__ __launch_bounds__(NT) void observe_kernel(EngineArgs a, double* values,
                                                      double* weights) {
   __shared__ Shared sh;
+  __shared__ z2 Jl[JCfg<RPL>::JB * JCfg<RPL>::LR];
   __shared__ double acc_obs[256];
   const int slot = blockIdx.x;
-  const Slot S = make_slot(a, slot);
+  const Slot S = make_slot(a, slot, Jl);
   load_state(a, slot, sh);
   const double obs_cut = 1e-30;    // gauge-only shifts
   for (int o = threadIdx.x; o < 256; o += NT) acc_obs[o] = 0.0;
-  while (sh.centre > 0) shift_left(S, sh.centre, obs_cut, sh);
-  double2* E = S.Y0;
-  double2* F = S.W;
+  while (sh.centre > 0) shift_left<RPL>(S, sh.centre, obs_cut, sh);
+  z2* E = S.Y0;
+  z2* F = S.W;
   for (int c = 0; c < (int)a.n; ++c) {
-    const double2* Ac = site(S, c);
+    const z2* Ac = site(S, c);
     const int cl = sh.bond[c], cr = sh.bond[c + 1];
     double nn = 0.0;
     for (int idx = threadIdx.x; idx < cl * 2 * cr; idx += NT)
@@ -809,16 +1010,16 @@ __global__ __launch_bounds__(NT) void observe_kernel(EngineArgs a, double* value
         E[idx] = cmk((idx / dl) == (idx % dl) ? 1.0 : 0.0, 0.0);
       __syncthreads();
       for (int k = c; k <= last; ++k) {
-        const double2* A = site(S, k);
+        const z2* A = site(S, k);
         const int kl = sh.bond[k], kr = sh.bond[k + 1];
         // operator on this site (product of the string's factors here)
-        double2 O[4] = {cmk(1, 0), cmk(0, 0), cmk(0, 0), cmk(1, 0)};
+        z2 O[4] = {cmk(1, 0), cmk(0, 0), cmk(0, 0), cmk(1, 0)};
         for (uint32_t t = 0; t < str.n_ops; ++t) {
           if (sh.site_of[str.q[t]] != k) continue;
-          double2 On[4];
+          z2 On[4];
           for (int r = 0; r < 2; ++r)
             for (int cc = 0; cc < 2; ++cc) {
-              double2 v = cmk(0, 0);
+              z2 v = cmk(0, 0);
               for (int m = 0; m < 2; ++m) cfma(v, pauli_el(str.p[t], r, m), O[m * 2 + cc]);
               On[r * 2 + cc] = v;
             }
@@ -827,7 +1028,7 @@ __global__ __launch_bounds__(NT) void observe_kernel(EngineArgs a, double* value
         // F[a', s, b] = sum_a E[a', a] A[a, s, b]
         for (int idx = threadIdx.x; idx < kl * 2 * kr; idx += NT) {
           const int ap = idx / (2 * kr), sb = idx - ap * 2 * kr;
-          double2 v = cmk(0, 0);
+          z2 v = cmk(0, 0);
           for (int aa = 0; aa < kl; ++aa) cfma(v, E[ap * kl + aa], A[(uint64_t)aa * 2 * kr + sb]);
           F[idx] = v;
         }
@@ -835,11 +1036,11 @@ __global__ __launch_bounds__(NT) void observe_kernel(EngineArgs a, double* value
         // E'[b', b] = sum_{a', s', s} conj(A[a', s', b']) O[s', s] F[a', s, b]
         for (int idx = threadIdx.x; idx < kr * kr; idx += NT) {
           const int bp = idx / kr, b = idx - bp * kr;
-          double2 v = cmk(0, 0);
+          z2 v = cmk(0, 0);
           for (int ap = 0; ap < kl; ++ap) {
-            const double2 f0 = F[(uint64_t)ap * 2 * kr + 0 * kr + b];
-            const double2 f1 = F[(uint64_t)ap * 2 * kr + 1 * kr + b];
-            double2 of0 = cmk(0, 0), of1 = cmk(0, 0);
+            const z2 f0 = F[(uint64_t)ap * 2 * kr + 0 * kr + b];
+            const z2 f1 = F[(uint64_t)ap * 2 * kr + 1 * kr + b];
+            z2 of0 = cmk(0, 0), of1 = cmk(0, 0);
             cfma(of0, O[0], f0);
             cfma(of0, O[1], f1);
             cfma(of1, O[2], f0);
@@ -860,7 +1061,7 @@ __global__ __launch_bounds__(NT) void observe_kernel(EngineArgs a, double* value
       if (threadIdx.x == 0) acc_obs[str.observable] += str.coeff * tr / norm2;
       __syncthreads();
     }
-    if (c + 1 < (int)a.n) shift_right(S, c, obs_cut, sh);
+    if (c + 1 < (int)a.n) shift_right<RPL>(S, c, obs_cut, sh);
   }
   __syncthreads();
   const SampleState* st = a.states + slot;
@@ -951,14 +1152,30 @@ hipError_t launch_init(const EngineArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Rows per lane needed for matrices of up to 2 chi_max rows.
+static int rows_per_lane(uint32_t chi_max) {
+  const uint32_t r = 2 * chi_max;
+  return r <= 64 ? 1 : r <= 128 ? 2 : r <= 256 ? 4 : 8;
+}
+
 hipError_t launch_evolve(const EngineArgs& a, uint32_t n_layers, hipStream_t s) {
-  hipLaunchKernelGGL(evolve_kernel, dim3(a.count), dim3(NT), 0, s, a, n_layers);
+  switch (rows_per_lane(a.chi_max)) {
+    case 1: hipLaunchKernelGGL(evolve_kernel<1>, dim3(a.count), dim3(NT), 0, s, a, n_layers); break;
+    case 2: hipLaunchKernelGGL(evolve_kernel<2>, dim3(a.count), dim3(NT), 0, s, a, n_layers); break;
+    case 4: hipLaunchKernelGGL(evolve_kernel<4>, dim3(a.count), dim3(NT), 0, s, a, n_layers); break;
+    default: hipLaunchKernelGGL(evolve_kernel<8>, dim3(a.count), dim3(NT), 0, s, a, n_layers); break;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_observe(const EngineArgs& a, double* d_values, double* d_weights,
                           hipStream_t s) {
-  hipLaunchKernelGGL(observe_kernel, dim3(a.count), dim3(NT), 0, s, a, d_values, d_weights);
+  switch (rows_per_lane(a.chi_max)) {
+    case 1: hipLaunchKernelGGL(observe_kernel<1>, dim3(a.count), dim3(NT), 0, s, a, d_values, d_weights); break;
+    case 2: hipLaunchKernelGGL(observe_kernel<2>, dim3(a.count), dim3(NT), 0, s, a, d_values, d_weights); break;
+    case 4: hipLaunchKernelGGL(observe_kernel<4>, dim3(a.count), dim3(NT), 0, s, a, d_values, d_weights); break;
+    default: hipLaunchKernelGGL(observe_kernel<8>, dim3(a.count), dim3(NT), 0, s, a, d_values, d_weights); break;
+  }
   return hipGetLastError();
 }
 

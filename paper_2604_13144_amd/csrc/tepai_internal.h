@@ -14,7 +14,7 @@ constexpr int kMaxQubits = 256;
 constexpr int kMaxChi = 256;
 constexpr int kMaxRows = 4096;        // PAI table rows per Trotter step
 constexpr int kMaxStringOps = 8;
-constexpr int kThreads = 256;         // engine block: four wave64 wavefronts
+constexpr int kThreads = 512;         // engine block: eight wave64 wavefronts
 constexpr int kMaxSweeps = 60;        // Jacobi sweep cap per factorisation
 
 // One row of the PAI table: a (sub-)rotation of one Trotter step.

@@ -174,6 +174,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
                      "kernel": "evolve_kernel",
+                     "kernel_ms_per_launch": evolve_ms / K,
+                     "flops_per_launch": d["nominal_flops"] / K,
                      "flops_model": "Golub-Reinsch nominal per update: 8*(2cl)*cm*(2cr) "
                                     "+ 4*(4m^2n+8mn^2+9n^3), m,n = 2cl,2cr"},
     }

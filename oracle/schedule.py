@@ -14,11 +14,16 @@ every path that claims parity with this oracle:
    one 4x4 operator and applied as ONE two-site update (one truncated SVD).  A run made only of pi
    rotations (C = -i P (x) P) is a product of local unitaries and is applied
    to the two site tensors without an SVD.
-3. A two-qubit operator whose qubits sit on non-adjacent sites (the ring's
-   wrap-around bond (n-1, 0)) is routed with SWAPs: the qubit on the higher
-   site moves down to the site just above the other one, one truncated
-   two-site SWAP update at a time, the operator is applied there, and the
-   qubit moves back up the same way.
+3. A two-qubit operator whose qubits sit on non-adjacent sites lo < hi (on a
+   ring kept as a chain these are the chain's two ends) is routed with SWAPs
+   and the chain is left in its new order: the end qubit nearer the
+   orthogonality centre (the one at hi when the centre is at or above the
+   midpoint (lo + hi) / 2) is carried past every qubit in between, one
+   truncated SWAP update at a time, and the last step is the single update
+   SWAP . G on the pair, which applies the operator and completes the move.
+   On a ring this rotates the chain by one site (hi - lo updates in all), so
+   every ring bond but one stays adjacent, and the next Trotter step goes on
+   from where the centre is.
 4. The orthogonality centre sits inside the two sites of every two-site
    update.  Before an update at sites (i, i+1) the centre moves to the nearer
    of i and i+1 by single-site SVD shifts that drop singular values
@@ -134,13 +139,23 @@ def build_schedule(problem, table, circuit, chi: Optional[int] = None) -> Tuple[
             return
         ia, ib = site_of[p.qa], site_of[p.qb]
         lo, hi = min(ia, ib), max(ia, ib)
-        for s in range(hi - 1, lo, -1):          # carry the upper qubit down
-            swap_sites(s, right=False)
+        if hi - lo == 1:
+            update(lo, p.M if ia < ib else flip_pair(p.M), right=True)
+            return
+        if 2 * centre[0] >= lo + hi:             # carry the upper qubit down
+            for s in range(hi - 1, lo, -1):      # ends next to the other qubit
+                swap_sites(s, right=False)
+            at = lo
+        else:                                    # carry the lower qubit up
+            for s in range(lo, hi - 1):
+                swap_sites(s, right=True)
+            at = hi - 1
         ia, ib = site_of[p.qa], site_of[p.qb]
         G = p.M if ia < ib else flip_pair(p.M)
-        update(lo, G, right=True)
-        for s in range(lo + 1, hi):              # and back up
-            swap_sites(s, right=True)
+        update(at, SWAP4 @ G, right=True)        # gate, then the last exchange
+        a, b = qubit_at[at], qubit_at[at + 1]
+        qubit_at[at], qubit_at[at + 1] = b, a
+        site_of[a], site_of[b] = at + 1, at
 
     pending: Optional[_Pending] = None
     for g, setting in zip(circuit.draws.tolist(), circuit.settings.tolist()):

@@ -108,6 +108,25 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// max into a non-negative LDS double (compare-and-swap on the bit pattern,
+// which orders like the value for non-negative doubles)
+__device__ __forceinline__ void atomicMax_double(double* a, double v) {
+  unsigned long long* p = reinterpret_cast<unsigned long long*>(a);
+  unsigned long long cur = *p;
+  const unsigned long long nv = (unsigned long long)__double_as_longlong(v);
+  while (nv > cur) {
+    const unsigned long long prev = atomicCAS(p, cur, nv);
+    if (prev == cur) break;
+    cur = prev;
+  }
+}
+
 // Move a double between lanes with a DPP control (both 32-bit halves).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
@@ -168,6 +187,7 @@ struct Shared {
   uint16_t site_of[kMaxQubits];
   uint8_t choice[kMaxRows];
   int flag;
+  double tmax;
   int p_active, p_has, p_qa, p_qb;
   int centre;
   // statistics (thread 0 writes)
@@ -228,10 +248,11 @@ __device__ __forceinline__ void rr_pair(int round, int k, int Cp, int& p, int& q
 // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2), s = c t,
 // x <- c x - s e^{-i phi} y, y <- s e^{i phi} x + c y, e^{i phi} = gamma/|gamma|.
 // Rows that are inactive or already orthogonal to tolerance leave both
-// columns untouched.  Returns whether this row rotated.
+// columns untouched.  Returns |t| = |tan| of the rotation angle, or -1 when
+// this row did not rotate.
 template <int E>
-__device__ __forceinline__ bool rotate_rows(z2 (&x)[E], lz2* y, int ea, int l16, bool active,
-                                            double tiny, double tol2) {
+__device__ __forceinline__ double rotate_rows(z2 (&x)[E], lz2* y, int ea, int l16, bool active,
+                                              double tiny, double tol2) {
   double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -249,6 +270,7 @@ __device__ __forceinline__ bool rotate_rows(z2 (&x)[E], lz2* y, int ea, int l16,
   gi = row16_sum(gi);
   const double g2 = gr * gr + gi * gi;
   const bool rot = active && al > tiny && be > tiny && g2 > tol2 * al * be;
+  double tabs = -1.0;
   if (rot) {
     const double ig = 1.0 / sqrt(g2);
     const double zeta = (be - al) * 0.5 * ig;
@@ -256,6 +278,7 @@ __device__ __forceinline__ bool rotate_rows(z2 (&x)[E], lz2* y, int ea, int l16,
     const double c = 1.0 / sqrt(1.0 + t * t);
     const double s = c * t;
     const double er = gr * ig, ei = gi * ig;
+    tabs = fabs(t);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       if (e < ea) {
@@ -267,7 +290,7 @@ __device__ __forceinline__ bool rotate_rows(z2 (&x)[E], lz2* y, int ea, int l16,
       }
     }
   }
-  return rot;
+  return tabs;
 }
 
 // Column <-> row registers.  From/to global memory only rows < R exist; the
@@ -352,9 +375,12 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
       }
       sh.order[rank] = (uint16_t)j;
     }
-    if (threadIdx.x == 0) sh.flag = 0;
+    if (threadIdx.x == 0) {
+      sh.flag = 0;
+      sh.tmax = 0.0;
+    }
     __syncthreads();
-    bool rot = false;
+    double tmx = -1.0;     // largest |tan| of the rotations this thread's row applied
 #pragma unroll 1
     for (int I = 0; I < nb; ++I) {
       const int pi = I * JB + row;                       // position of this row's column
@@ -385,7 +411,7 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
         for (int rr = 0; rr < JB; ++rr) {
           const int jj = (row + rr) % JB;
           const bool act = ai && J * JB + jj < C;
-          if (row < JB) rot |= rotate_rows<E>(xi, Jl + jj * LR, ea, l16, act, tiny, tol2);
+          if (row < JB) tmx = fmax(tmx, rotate_rows<E>(xi, Jl + jj * LR, ea, l16, act, tiny, tol2));
           __syncthreads();
         }
         if (row < JB && J * JB + row < C) {
@@ -407,9 +433,10 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
           const bool act = I * JB + q < C;
           z2 x[E];
           row_load_l<E>(x, Jl + p * LR, ea, l16);
-          if (rotate_rows<E>(x, Jl + q * LR, ea, l16, act, tiny, tol2)) {
+          const double t = rotate_rows<E>(x, Jl + q * LR, ea, l16, act, tiny, tol2);
+          if (t >= 0.0) {
             row_store_l<E>(x, Jl + p * LR, ea, l16);
-            rot = true;
+            tmx = fmax(tmx, t);
           }
         }
         __syncthreads();
@@ -424,11 +451,20 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
       }
       __syncthreads();
     }
-    if (rot) sh.flag = 1;
+    // Stop when no pair rotated, or when every rotation of this sweep turned
+    // by |tan| <= 1e-8: the columns then moved by at most 1e-8 of their
+    // partners, so the non-orthogonality left behind is ~1e-16 and a further
+    // sweep would find nothing above the tolerance.
+    tmx = wave_max(tmx);
+    if ((threadIdx.x & 63) == 0 && tmx >= 0.0) {
+      sh.flag = 1;
+      atomicMax_double(&sh.tmax, tmx);
+    }
     __syncthreads();
     const int rotated = sh.flag;
+    const double tm = sh.tmax;
     __syncthreads();
-    if (!rotated) return sweep;
+    if (!rotated || tm <= 1e-8) return sweep;
   }
   return -1;
 }
@@ -739,21 +775,43 @@ __device__ void flush(const Slot& S, Shared& sh) {
     apply_local(S, sh.site_of[qa], Ua, sh);
     apply_local(S, sh.site_of[qb], Ub, sh);
   } else {
+    // Non-adjacent pair (the two ends of a ring kept as a chain): carry the
+    // end qubit nearer the centre across, the last step being SWAP . G on
+    // the pair; the chain keeps its new order (a rotation of the ring).
     int ia = sh.site_of[qa], ib = sh.site_of[qb];
     const int lo = ia < ib ? ia : ib, hi = ia < ib ? ib : ia;
-    for (int s = hi - 1; s > lo; --s) swap_sites<RPL>(S, s, false, sh);
-    ia = sh.site_of[qa];
-    ib = sh.site_of[qb];
+    int at = lo;
+    const bool carry = hi - lo > 1;
+    if (carry) {
+      if (2 * sh.centre >= lo + hi) {
+        for (int s = hi - 1; s > lo; --s) swap_sites<RPL>(S, s, false, sh);
+        at = lo;
+      } else {
+        for (int s = lo; s < hi - 1; ++s) swap_sites<RPL>(S, s, true, sh);
+        at = hi - 1;
+      }
+      ia = sh.site_of[qa];
+      ib = sh.site_of[qb];
+    }
     if (threadIdx.x < 16) {
-      const int r = threadIdx.x >> 2, c = threadIdx.x & 3;
+      int r = threadIdx.x >> 2;
+      const int c = threadIdx.x & 3;
+      if (carry) r = ((r & 1) << 1) | (r >> 1);   // rows of SWAP . G
       // exchange tensor factors when qa sits on the right site
       const int rr = ia < ib ? r : ((r & 1) << 1 | (r >> 1));
       const int cc = ia < ib ? c : ((c & 1) << 1 | (c >> 1));
       sh.G[threadIdx.x] = sh.pM[rr * 4 + cc];
     }
     __syncthreads();
-    two_site<RPL>(S, lo, true, false, sh);
-    for (int s = lo + 1; s < hi; ++s) swap_sites<RPL>(S, s, true, sh);
+    two_site<RPL>(S, at, true, false, sh);
+    if (carry && threadIdx.x == 0) {
+      const int a = sh.qubit_at[at], b = sh.qubit_at[at + 1];
+      sh.qubit_at[at] = (uint16_t)b;
+      sh.qubit_at[at + 1] = (uint16_t)a;
+      sh.site_of[a] = (uint16_t)(at + 1);
+      sh.site_of[b] = (uint16_t)at;
+    }
+    __syncthreads();
   }
   if (threadIdx.x == 0) sh.p_active = 0;
   __syncthreads();
@@ -846,8 +904,9 @@ __device__ void load_state(const EngineArgs& a, int slot, Shared& sh) {
   const SampleState* st = a.states + slot;
   for (int k = threadIdx.x; k <= (int)a.n; k += NT) sh.bond[k] = st->bond[k];
   for (int k = threadIdx.x; k < (int)a.n; k += NT) {
-    sh.qubit_at[k] = (uint16_t)k;
-    sh.site_of[k] = (uint16_t)k;
+    const uint16_t q = st->qubit_at[k];
+    sh.qubit_at[k] = q;
+    sh.site_of[q] = (uint16_t)k;
   }
   if (threadIdx.x == 0) {
     sh.centre = st->centre;
@@ -873,6 +932,7 @@ __device__ void load_state(const EngineArgs& a, int slot, Shared& sh) {
 __device__ void store_state(const EngineArgs& a, int slot, Shared& sh, uint32_t layer) {
   SampleState* st = a.states + slot;
   for (int k = threadIdx.x; k <= (int)a.n; k += NT) st->bond[k] = sh.bond[k];
+  for (int k = threadIdx.x; k < (int)a.n; k += NT) st->qubit_at[k] = sh.qubit_at[k];
   if (threadIdx.x == 0) {
     st->centre = sh.centre;
     st->updates = sh.updates;
@@ -919,6 +979,7 @@ __global__ __launch_bounds__(NT) void init_kernel(EngineArgs a) {
     T[(uint64_t)k * a.site_stride + 1] = cmk(bit ? 1.0 : 0.0, 0.0);
   }
   for (int k = threadIdx.x; k <= (int)a.n; k += NT) st->bond[k] = 1;
+  for (int k = threadIdx.x; k < (int)a.n; k += NT) st->qubit_at[k] = (uint16_t)k;
   if (threadIdx.x == 0) {
     st->centre = 0;
     st->chi_cap = a.chi_caps[slot];

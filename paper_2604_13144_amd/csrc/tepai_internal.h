@@ -45,6 +45,7 @@ struct SampleState {
   uint64_t n_gates, updates, swap_updates, shifts, sweeps, nonconverged, ties;
   double sum_chi3, nominal_flops, discarded, max_discarded, min_gap;
   uint16_t bond[kMaxQubits + 1];   // bond[k] = dimension between sites k-1 and k
+  uint16_t qubit_at[kMaxQubits];   // chain order: qubit held by each site
 };
 
 // Everything a kernel launch needs; passed by value.

@@ -127,6 +127,23 @@ __device__ __forceinline__ void atomicMax_double(double* a, double v) {
   }
 }
 
+
+// 1/sqrt(x) and 1/x from the hardware estimates refined by two Newton steps
+// (each step squares the relative error) for the rotation parameters.
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * fma(-x, y, 2.0);
+  y = y * fma(-x, y, 2.0);
+  return y;
+}
+
 // Move a double between lanes with a DPP control (both 32-bit halves).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
@@ -240,8 +257,8 @@ __device__ __forceinline__ void rr_pair(int round, int k, int Cp, int& p, int& q
 
 // One Jacobi rotation per 16-lane row: the row's lanes hold E elements each
 // of the column x in registers (element e of lane l is matrix row l + 16 e)
-// and read the partner column y from LDS twice (inner products, then the
-// update), which keeps register use at one column per row.  Only the first
+// and the partner column y is read from LDS once and held in registers
+// between the inner products and the update.  Only the first
 // ea = ceil(R / 16) elements are touched (a wave-uniform bound); rows of the
 // last element beyond R hold zeros and stay zero.
 // gamma = x^H y, zeta = (|y|^2 - |x|^2) / (2 |gamma|),
@@ -254,10 +271,12 @@ template <int E>
 __device__ __forceinline__ double rotate_rows(z2 (&x)[E], lz2* y, int ea, int l16, bool active,
                                               double tiny, double tol2) {
   double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+  z2 yv[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     if (e < ea) {
       const z2 b = y[l16 + 16 * e];
+      yv[e] = b;
       al = fma(x[e].x, x[e].x, fma(x[e].y, x[e].y, al));
       be = fma(b.x, b.x, fma(b.y, b.y, be));
       gr = fma(x[e].x, b.x, fma(x[e].y, b.y, gr));
@@ -272,17 +291,19 @@ __device__ __forceinline__ double rotate_rows(z2 (&x)[E], lz2* y, int ea, int l1
   const bool rot = active && al > tiny && be > tiny && g2 > tol2 * al * be;
   double tabs = -1.0;
   if (rot) {
-    const double ig = 1.0 / sqrt(g2);
+    const double ig = rsq_nr(g2);
     const double zeta = (be - al) * 0.5 * ig;
-    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-    const double c = 1.0 / sqrt(1.0 + t * t);
+    const double q = 1.0 + zeta * zeta;
+    const double hq = q * rsq_nr(q);
+    const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(zeta) + hq);
+    const double c = rsq_nr(1.0 + t * t);
     const double s = c * t;
     const double er = gr * ig, ei = gi * ig;
     tabs = fabs(t);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       if (e < ea) {
-        const z2 a = x[e], b = y[l16 + 16 * e];
+        const z2 a = x[e], b = yv[e];
         const z2 eb = cmk(er * b.x + ei * b.y, er * b.y - ei * b.x);   // e^{-i phi} y
         const z2 ex = cmk(er * a.x - ei * a.y, er * a.y + ei * a.x);   // e^{i phi} x
         x[e] = cmk(c * a.x - s * eb.x, c * a.y - s * eb.y);
@@ -407,11 +428,25 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
           row_store_l<E>(y, Jl + row * LR, ea, l16);
         }
         __syncthreads();
+        // Cross pairs in 4 x 4 tiles: wave w (rows 4w..4w+3) owns I-tile w and
+        // visits the J-tiles (w + R) mod NTILE; inside a tile its four rows
+        // meet the four J columns in four wave-local rounds (LDS is in order
+        // within a wave), so the workgroup synchronises once per tile
+        // rotation instead of once per round.
+        constexpr int NTILE = JB / 4;
+        const int wv = row >> 2, r4 = row & 3;
 #pragma unroll 1
-        for (int rr = 0; rr < JB; ++rr) {
-          const int jj = (row + rr) % JB;
-          const bool act = ai && J * JB + jj < C;
-          if (row < JB) tmx = fmax(tmx, rotate_rows<E>(xi, Jl + jj * LR, ea, l16, act, tiny, tol2));
+        for (int Rr = 0; Rr < NTILE; ++Rr) {
+          if (wv < NTILE) {
+            const int tb = (wv + Rr) % NTILE;
+#pragma unroll 1
+            for (int r = 0; r < 4; ++r) {
+              const int jj = 4 * tb + ((r4 + r) & 3);
+              const bool act = ai && J * JB + jj < C;
+              tmx = fmax(tmx, rotate_rows<E>(xi, Jl + jj * LR, ea, l16, act, tiny, tol2));
+              __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            }
+          }
           __syncthreads();
         }
         if (row < JB && J * JB + row < C) {

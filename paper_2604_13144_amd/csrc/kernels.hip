@@ -47,6 +47,7 @@ struct JCfg {
 typedef double z2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) z2 lz2;
 typedef __attribute__((address_space(1))) z2 gz2;
+typedef __attribute__((address_space(3))) double ld;
 
 __device__ __forceinline__ z2 cmk(double r, double i) {
   z2 v;
@@ -196,6 +197,7 @@ struct Shared {
   z2 pLa[4], pLb[4];     // its local factors while it holds only C settings
   z2 pPhase;
   double sig2[2 * kMaxChi];   // squared column norms after Jacobi
+  double jn[NROWS];           // squared norms of the columns staged in LDS
   double red[NW * 4];
   uint16_t perm[2 * kMaxChi]; // columns by descending norm
   uint16_t order[2 * kMaxChi];// Jacobi sweep order
@@ -255,60 +257,185 @@ __device__ __forceinline__ void rr_pair(int round, int k, int Cp, int& p, int& q
   }
 }
 
+// Sum over G consecutive 16-lane rows of a wave (G = 1, 2, 4).  The 16-lane
+// sum is symmetric (row16_sum); the row pairs then exchange with the gfx950
+// permlane swaps (rows 2k <-> 2k+1, then halves), and both partners add the
+// same two operands in the same order, so all G rows end bitwise-equal.
+template <int W>
+__device__ __forceinline__ double swap_add(double v) {
+  const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+  if constexpr (W == 16) {
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+  } else {
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+  }
+}
+
+template <int G>
+__device__ __forceinline__ double rows_sum(double v) {
+  v = row16_sum(v);
+  if constexpr (G >= 2) v = swap_add<16>(v);
+  if constexpr (G >= 4) v = swap_add<32>(v);
+  return v;
+}
+
+// Rotation parameters from alpha = |x|^2, beta = |y|^2, gamma = x^H y:
+// zeta = (beta - alpha) / (2 |gamma|), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+// c = 1/sqrt(1+t^2), s = c t, e^{i phi} = gamma/|gamma|.  The rotation
+// x <- c x - s e^{-i phi} y, y <- s e^{i phi} x + c y zeroes x^H y and moves
+// t |gamma| of squared norm from x to y: |x'|^2 = alpha - t|gamma|,
+// |y'|^2 = beta + t|gamma| (the two-sided Jacobi update of the 2 x 2 Gram
+// matrix).
+struct Rot {
+  double c, s, er, ei, t, tg;
+};
+
+__device__ __forceinline__ Rot rot_params(double al, double be, double gr, double gi, double g2) {
+  Rot r;
+  const double ig = rsq_nr(g2);
+  const double zeta = (be - al) * 0.5 * ig;
+  const double q = 1.0 + zeta * zeta;
+  const double hq = q * rsq_nr(q);
+  r.t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(zeta) + hq);
+  r.c = rsq_nr(1.0 + r.t * r.t);
+  r.s = r.c * r.t;
+  r.er = gr * ig;
+  r.ei = gi * ig;
+  r.tg = r.t * (g2 * ig);
+  return r;
+}
+
+__device__ __forceinline__ void rot_apply(const Rot& r, z2& a, z2& b) {
+  const z2 x = a, y = b;
+  const z2 eb = cmk(r.er * y.x + r.ei * y.y, r.er * y.y - r.ei * y.x);   // e^{-i phi} y
+  const z2 ex = cmk(r.er * x.x - r.ei * x.y, r.er * x.y + r.ei * x.x);   // e^{i phi} x
+  a = cmk(r.c * x.x - r.s * eb.x, r.c * x.y - r.s * eb.y);
+  b = cmk(r.s * ex.x + r.c * y.x, r.s * ex.y + r.c * y.y);
+}
+
+// A squared norm carried through rotations by the update above loses
+// accuracy when most of it cancels; below this fraction of its previous
+// value it is recomputed from the column.
+constexpr double kNormRecompute = 0.25;
+
 // One Jacobi rotation per 16-lane row: the row's lanes hold E elements each
 // of the column x in registers (element e of lane l is matrix row l + 16 e)
-// and the partner column y is read from LDS once and held in registers
-// between the inner products and the update.  Only the first
-// ea = ceil(R / 16) elements are touched (a wave-uniform bound); rows of the
-// last element beyond R hold zeros and stay zero.
-// gamma = x^H y, zeta = (|y|^2 - |x|^2) / (2 |gamma|),
-// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2), s = c t,
-// x <- c x - s e^{-i phi} y, y <- s e^{i phi} x + c y, e^{i phi} = gamma/|gamma|.
-// Rows that are inactive or already orthogonal to tolerance leave both
-// columns untouched.  Returns |t| = |tan| of the rotation angle, or -1 when
-// this row did not rotate.
+// with its squared norm al; the partner column y is read from LDS once and
+// held in registers between the inner product and the update, and its
+// squared norm lives in LDS at yn.  Only the first ea = ceil(R / 16)
+// elements are touched (a wave-uniform bound).  Rows that are inactive or
+// already orthogonal to tolerance leave both columns untouched.  Returns
+// |t| = |tan| of the rotation angle, or -1 when this row did not rotate.
 template <int E>
-__device__ __forceinline__ double rotate_rows(z2 (&x)[E], lz2* y, int ea, int l16, bool active,
-                                              double tiny, double tol2) {
-  double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+__device__ __forceinline__ double rotate_rows(z2 (&x)[E], double& al, lz2* y, ld* yn, int ea,
+                                              int l16, bool active, double tiny, double tol2) {
+  double gr = 0.0, gi = 0.0;
   z2 yv[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     if (e < ea) {
       const z2 b = y[l16 + 16 * e];
       yv[e] = b;
-      al = fma(x[e].x, x[e].x, fma(x[e].y, x[e].y, al));
-      be = fma(b.x, b.x, fma(b.y, b.y, be));
       gr = fma(x[e].x, b.x, fma(x[e].y, b.y, gr));
       gi = fma(x[e].x, b.y, fma(-x[e].y, b.x, gi));
     }
   }
-  al = row16_sum(al);
-  be = row16_sum(be);
   gr = row16_sum(gr);
   gi = row16_sum(gi);
+  const double be = *yn;
   const double g2 = gr * gr + gi * gi;
   const bool rot = active && al > tiny && be > tiny && g2 > tol2 * al * be;
   double tabs = -1.0;
   if (rot) {
-    const double ig = rsq_nr(g2);
-    const double zeta = (be - al) * 0.5 * ig;
-    const double q = 1.0 + zeta * zeta;
-    const double hq = q * rsq_nr(q);
-    const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(zeta) + hq);
-    const double c = rsq_nr(1.0 + t * t);
-    const double s = c * t;
-    const double er = gr * ig, ei = gi * ig;
-    tabs = fabs(t);
+    const Rot r = rot_params(al, be, gr, gi, g2);
+    tabs = fabs(r.t);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       if (e < ea) {
-        const z2 a = x[e], b = yv[e];
-        const z2 eb = cmk(er * b.x + ei * b.y, er * b.y - ei * b.x);   // e^{-i phi} y
-        const z2 ex = cmk(er * a.x - ei * a.y, er * a.y + ei * a.x);   // e^{i phi} x
-        x[e] = cmk(c * a.x - s * eb.x, c * a.y - s * eb.y);
-        y[l16 + 16 * e] = cmk(s * ex.x + c * b.x, s * ex.y + c * b.y);
+        rot_apply(r, x[e], yv[e]);
+        y[l16 + 16 * e] = yv[e];
       }
+    }
+    double an = al - r.tg, bn = be + r.tg;
+    if (an < kNormRecompute * al) {
+      double a = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) a = fma(x[e].x, x[e].x, fma(x[e].y, x[e].y, a));
+      an = row16_sum(a);
+    }
+    if (bn < kNormRecompute * be) {
+      double a = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if (e < ea) a = fma(yv[e].x, yv[e].x, fma(yv[e].y, yv[e].y, a));
+      bn = row16_sum(a);
+    }
+    al = an;
+    if (l16 == 0) *yn = bn;
+  }
+  return tabs;
+}
+
+// One rotation of the LDS columns xp and yq, shared by G consecutive rows of
+// a wave: the row with part h (e0 = h EG) handles elements [e0, e0 + EG) of
+// both columns (EG = E / G), and the inner product and any norm
+// recomputation are summed over the G rows.  The squared norms live in LDS
+// at pn and qn; the part-0 row writes their updates.
+template <int EG, int G>
+__device__ __forceinline__ double rotate_split(lz2* xp, lz2* yq, ld* pn, ld* qn, int e0,
+                                               int ea, int l16, bool first, bool active,
+                                               double tiny, double tol2) {
+  z2 xv[EG], yv[EG];
+  double gr = 0.0, gi = 0.0;
+#pragma unroll
+  for (int e = 0; e < EG; ++e) {
+    if (e0 + e < ea) {
+      xv[e] = xp[l16 + 16 * (e0 + e)];
+      yv[e] = yq[l16 + 16 * (e0 + e)];
+    } else {
+      xv[e] = cmk(0.0, 0.0);
+      yv[e] = cmk(0.0, 0.0);
+    }
+    gr = fma(xv[e].x, yv[e].x, fma(xv[e].y, yv[e].y, gr));
+    gi = fma(xv[e].x, yv[e].y, fma(-xv[e].y, yv[e].x, gi));
+  }
+  gr = rows_sum<G>(gr);
+  gi = rows_sum<G>(gi);
+  const double al = *pn, be = *qn;
+  const double g2 = gr * gr + gi * gi;
+  const bool rot = active && al > tiny && be > tiny && g2 > tol2 * al * be;
+  double tabs = -1.0;
+  if (rot) {
+    const Rot r = rot_params(al, be, gr, gi, g2);
+    tabs = fabs(r.t);
+#pragma unroll
+    for (int e = 0; e < EG; ++e) {
+      rot_apply(r, xv[e], yv[e]);
+      if (e0 + e < ea) {
+        xp[l16 + 16 * (e0 + e)] = xv[e];
+        yq[l16 + 16 * (e0 + e)] = yv[e];
+      }
+    }
+    double an = al - r.tg, bn = be + r.tg;
+    if (an < kNormRecompute * al) {
+      double a = 0.0;
+#pragma unroll
+      for (int e = 0; e < EG; ++e) a = fma(xv[e].x, xv[e].x, fma(xv[e].y, xv[e].y, a));
+      an = rows_sum<G>(a);
+    }
+    if (bn < kNormRecompute * be) {
+      double a = 0.0;
+#pragma unroll
+      for (int e = 0; e < EG; ++e) a = fma(yv[e].x, yv[e].x, fma(yv[e].y, yv[e].y, a));
+      bn = rows_sum<G>(a);
+    }
+    if (first && l16 == 0) {
+      *pn = an;
+      *qn = bn;
     }
   }
   return tabs;
@@ -365,6 +492,7 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
   constexpr int E = K::E, JB = K::JB, LR = K::LR;
   gz2* W = (gz2*)W_;
   lz2* Jl = (lz2*)Jl_;
+  ld* jn = (ld*)sh.jn;
   const int l16 = threadIdx.x & 15, row = threadIdx.x >> 4;
   const int ea = (R + 15) >> 4;
   if (C < 2) return 0;
@@ -414,6 +542,7 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
 #pragma unroll
         for (int e = 0; e < E; ++e) xi[e] = cmk(0.0, 0.0);
       }
+      double al = row_norm2<E>(xi);      // carried through the rotations
 #pragma unroll 1
       for (int J = I + 1; J < nb; ++J) {
         if (row < JB) {   // stage block J: one column per row
@@ -426,6 +555,8 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
             for (int e = 0; e < E; ++e) y[e] = cmk(0.0, 0.0);
           }
           row_store_l<E>(y, Jl + row * LR, ea, l16);
+          const double b = row_norm2<E>(y);
+          if (l16 == 0) jn[row] = b;
         }
         __syncthreads();
         // Cross pairs in 4 x 4 tiles: wave w (rows 4w..4w+3) owns I-tile w and
@@ -443,7 +574,7 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
             for (int r = 0; r < 4; ++r) {
               const int jj = 4 * tb + ((r4 + r) & 3);
               const bool act = ai && J * JB + jj < C;
-              tmx = fmax(tmx, rotate_rows<E>(xi, Jl + jj * LR, ea, l16, act, tiny, tol2));
+              tmx = fmax(tmx, rotate_rows<E>(xi, al, Jl + jj * LR, jn + jj, ea, l16, act, tiny, tol2));
               __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
             }
           }
@@ -456,25 +587,26 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
         }
         __syncthreads();
       }
-      // pairs inside block I, in LDS (round-robin over the JB columns)
-      if (row < JB) row_store_l<E>(xi, Jl + row * LR, ea, l16);
+      // pairs inside block I, in LDS (round-robin over the JB columns); each
+      // of the JB/2 pairs of a round is shared by G rows of one wave, so
+      // every row of the workgroup works
+      if (row < JB) {
+        row_store_l<E>(xi, Jl + row * LR, ea, l16);
+        if (l16 == 0) jn[row] = al;
+      }
       __syncthreads();
+      {
+        constexpr int G = NROWS / (JB / 2), EG = E / G;
+        const int k = row / G, h = row - k * G;
 #pragma unroll 1
-      for (int round = 0; round < JB - 1; ++round) {
-        const bool on = row < JB / 2;
-        if (on) {
+        for (int round = 0; round < JB - 1; ++round) {
           int p, q;
-          rr_pair(round, row, JB, p, q);
+          rr_pair(round, k, JB, p, q);
           const bool act = I * JB + q < C;
-          z2 x[E];
-          row_load_l<E>(x, Jl + p * LR, ea, l16);
-          const double t = rotate_rows<E>(x, Jl + q * LR, ea, l16, act, tiny, tol2);
-          if (t >= 0.0) {
-            row_store_l<E>(x, Jl + p * LR, ea, l16);
-            tmx = fmax(tmx, t);
-          }
+          tmx = fmax(tmx, rotate_split<EG, G>(Jl + p * LR, Jl + q * LR, jn + p, jn + q, h * EG,
+                                               ea, l16, h == 0, act, tiny, tol2));
+          __syncthreads();
         }
-        __syncthreads();
       }
       // write block I back and record its final column norms for the next order
       if (ai) {

@@ -201,6 +201,9 @@ struct Shared {
   double red[NW * 4];
   uint16_t perm[2 * kMaxChi]; // columns by descending norm
   uint16_t order[2 * kMaxChi];// Jacobi sweep order
+  uint16_t piv[2 * kMaxChi];  // column pivots of the QR preconditioner
+  int qr_p;
+  double qr_v, qr_k;
   uint16_t bond[kMaxQubits + 1];
   uint16_t qubit_at[kMaxQubits];
   uint16_t site_of[kMaxQubits];
@@ -636,18 +639,191 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
   return -1;
 }
 
+// ------------------------------------------------- QR preconditioning
+// Householder QR with column pivoting of Z (nr x nc, column-major, global):
+// Z P = Q Rz.  On return the upper trapezoid of Z holds Rz and sh.piv[j] is
+// the original index of the column at position j; Q is not formed and the
+// part below the diagonal is scratch.  Step j takes as pivot the remaining
+// column with the largest norm below row j (lowest index on ties); those
+// norms are recomputed from the updated columns in the same pass that applies
+// the reflector, so no norm downdating is needed.  The reflector for
+// x = Z[j:, j], x_0 = |x_0| e^{i phi}: beta = -e^{i phi} |x|, u = x - beta e_0,
+// H = I - kappa u u^H with kappa = 1 / (|x| (|x| + |x_0|)); H is unitary and
+// Hermitian and maps x to beta e_0, so H y = y - kappa (u^H y) u.
+template <int RPL>
+__device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_) {
+  constexpr int E = 4 * RPL;
+  gz2* Z = (gz2*)Z_;
+  lz2* Ul = (lz2*)Ul_;
+  ld* vn = (ld*)sh.sig2;
+  const int l16 = threadIdx.x & 15, row = threadIdx.x >> 4;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int eall = (nr + 15) >> 4;
+#pragma unroll 1
+  for (int i = row; i < nc; i += NROWS) {
+    const gz2* col = Z + (uint64_t)i * nr;
+    double a = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int r = l16 + 16 * e;
+      if (e < eall && r < nr) {
+        const z2 v = col[r];
+        a = fma(v.x, v.x, fma(v.y, v.y, a));
+      }
+    }
+    a = row16_sum(a);
+    if (l16 == 0) vn[i] = a;
+  }
+  for (int i = threadIdx.x; i < nc; i += NT) sh.piv[i] = (uint16_t)i;
+  __syncthreads();
+  const int m = nr < nc ? nr : nc;
+#pragma unroll 1
+  for (int j = 0; j < m; ++j) {
+    if (wv == 0) {
+      double best = -1.0;
+      int bi = nc;
+      for (int i = j + lane; i < nc; i += 64) {
+        const double v = vn[i];
+        if (v > best) {
+          best = v;
+          bi = i;
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        sh.qr_p = bi;
+        sh.qr_v = best;
+      }
+    }
+    __syncthreads();
+    const int p = sh.qr_p;
+    if (!(sh.qr_v > 0.0)) break;      // every remaining column is zero
+    if (p != j) {
+      gz2* a = Z + (uint64_t)j * nr;
+      gz2* b = Z + (uint64_t)p * nr;
+      for (int r = threadIdx.x; r < nr; r += NT) {
+        const z2 t = a[r];
+        a[r] = b[r];
+        b[r] = t;
+      }
+      if (threadIdx.x == 0) {
+        const double t = vn[j];
+        vn[j] = vn[p];
+        vn[p] = t;
+        const uint16_t q = sh.piv[j];
+        sh.piv[j] = sh.piv[p];
+        sh.piv[p] = q;
+      }
+    }
+    __syncthreads();
+    if (wv == 0) {
+      gz2* col = Z + (uint64_t)j * nr;
+      const z2 a0 = col[j];
+      const double aa = sqrt(a0.x * a0.x + a0.y * a0.y);
+      const double xn = sqrt(vn[j]);
+      const z2 ph = aa > 0.0 ? cmk(a0.x / aa, a0.y / aa) : cmk(1.0, 0.0);
+      for (int r = j + lane; r < nr; r += 64)
+        Ul[r] = r == j ? cmk(ph.x * (aa + xn), ph.y * (aa + xn)) : col[r];
+      if (lane == 0) {
+        col[j] = cmk(-ph.x * xn, -ph.y * xn);
+        sh.qr_k = 1.0 / (xn * (xn + aa));
+      }
+    }
+    __syncthreads();
+    const double kap = sh.qr_k;
+    const int ea = (nr - j + 15) >> 4;
+    z2 uv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int r = j + l16 + 16 * e;
+      uv[e] = (e < ea && r < nr) ? (z2)Ul[r] : cmk(0.0, 0.0);
+    }
+#pragma unroll 1
+    for (int i = j + 1 + row; i < nc; i += NROWS) {
+      gz2* col = Z + (uint64_t)i * nr;
+      z2 z[E];
+      double gr = 0.0, gi = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int r = j + l16 + 16 * e;
+        z[e] = (e < ea && r < nr) ? (z2)col[r] : cmk(0.0, 0.0);
+        gr = fma(uv[e].x, z[e].x, fma(uv[e].y, z[e].y, gr));
+        gi = fma(uv[e].x, z[e].y, fma(-uv[e].y, z[e].x, gi));
+      }
+      gr = row16_sum(gr) * kap;
+      gi = row16_sum(gi) * kap;
+      double a = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int r = j + l16 + 16 * e;
+        if (e < ea && r < nr) {
+          const z2 u = uv[e];
+          const z2 v = cmk(z[e].x - (gr * u.x - gi * u.y), z[e].y - (gr * u.y + gi * u.x));
+          col[r] = v;
+          if (r > j) a = fma(v.x, v.x, fma(v.y, v.y, a));
+        }
+      }
+      a = row16_sum(a);
+      if (l16 == 0) vn[i] = a;
+    }
+    __syncthreads();
+  }
+}
+
+// Left singular vectors of M (R x C, column-major in Y0): Z = M^H is
+// factored as Z P = Q Rz (in W), one-sided Jacobi orthogonalises the m
+// columns of X = Rz^H (R x m, m = min(R, C), in the buffer X), and since
+// M = P X Q^H, the columns of X with their rows put back by P are the left
+// singular vectors of M times the singular values; they are written to W
+// (R x m, column-major).  The pivoted QR concentrates the norm in the leading
+// columns, which cuts the number of Jacobi sweeps (Drmac and Veselic's QR
+// preconditioning of one-sided Jacobi).  Returns the sweeps (-1 at the cap).
+template <int RPL>
+__device__ int svd_cols(z2* W, const z2* Y0, z2* X, int R, int C, Shared& sh, z2* Jl) {
+  for (int idx = threadIdx.x; idx < R * C; idx += NT) {
+    const int c = idx / R, r = idx - c * R;
+    W[(uint64_t)r * C + c] = cconj(Y0[idx]);
+  }
+  __syncthreads();
+  qrcp<RPL>(W, C, R, sh, Jl);
+  const int m = R < C ? R : C;
+  for (int idx = threadIdx.x; idx < R * m; idx += NT) {
+    const int jj = idx / R, r = idx - jj * R;
+    X[idx] = jj <= r ? cconj(W[(uint64_t)r * C + jj]) : cmk(0.0, 0.0);
+  }
+  __syncthreads();
+  const int sweeps = jacobi<RPL>(X, R, m, sh, Jl);
+  for (int idx = threadIdx.x; idx < R * m; idx += NT) {
+    const int jj = idx / R, r = idx - jj * R;
+    W[(uint64_t)jj * R + sh.piv[r]] = X[idx];
+  }
+  __syncthreads();
+  return sweeps;
+}
+
 struct Factor {
   int k;          // kept singular values
   double scale;   // 1 / ||sigma_kept||
 };
 
-// Jacobi SVD of W (R x C), sort, choose k = min(cap, #{sigma > cutoff sigma_0}),
-// record statistics.  sh.perm[j] is the column of the j-th largest sigma.
+// SVD of M = Y0 (R x C): the columns of W become the left singular vectors
+// times the singular values (svd_cols, with X as scratch); sort, choose
+// k = min(cap, #{sigma > cutoff sigma_0}), record statistics.  sh.perm[j] is
+// the column of W holding the j-th largest sigma.
 template <int RPL>
-__device__ Factor factorise(z2* W, int R, int C, int cap, double cutoff, bool record,
-                            Shared& sh, z2* Jl) {
+__device__ Factor factorise(z2* W, const z2* Y0, z2* X, int R, int C_, int cap, double cutoff,
+                            bool record, Shared& sh, z2* Jl) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int sweeps = jacobi<RPL>(W, R, C, sh, Jl);
+  const int sweeps = svd_cols<RPL>(W, Y0, X, R, C_, sh, Jl);
+  const int C = R < C_ ? R : C_;     // columns of W from here on
   for (int j = wv; j < C; j += NW) {
     const z2* w = W + (uint64_t)j * R;
     double a = 0.0;
@@ -746,12 +922,10 @@ __device__ void shift_right(const Slot& S, int c, double cutoff, Shared& sh) {
   const int R = 2 * cl, C = cr;
   for (int idx = threadIdx.x; idx < R * C; idx += NT) {
     const int row = idx / C, col = idx - row * C;
-    const z2 v = A[idx];
-    S.Y0[(uint64_t)col * R + row] = v;
-    S.W[(uint64_t)col * R + row] = v;
+    S.Y0[(uint64_t)col * R + row] = A[idx];
   }
   __syncthreads();
-  const Factor f = factorise<RPL>(S.W, R, C, C, cutoff, false, sh, S.Jl);
+  const Factor f = factorise<RPL>(S.W, S.Y0, S.P, R, C, C, cutoff, false, sh, S.Jl);
   const int k = f.k;
   project(S.W, S.Y0, S.P, R, C, k, sh);
   for (int idx = threadIdx.x; idx < R * k; idx += NT) {
@@ -786,12 +960,10 @@ __device__ void shift_left(const Slot& S, int c, double cutoff, Shared& sh) {
   const int cl = sh.bond[c], cr = sh.bond[c + 1], cl0 = sh.bond[c - 1];
   const int R = 2 * cr, C = cl;
   for (int idx = threadIdx.x; idx < R * C; idx += NT) {
-    const z2 v = cconj(A[idx]);      // Y = A^H, same memory order
-    S.Y0[idx] = v;
-    S.W[idx] = v;
+    S.Y0[idx] = cconj(A[idx]);      // Y = A^H, same memory order
   }
   __syncthreads();
-  const Factor f = factorise<RPL>(S.W, R, C, C, cutoff, false, sh, S.Jl);
+  const Factor f = factorise<RPL>(S.W, S.Y0, S.P, R, C, C, cutoff, false, sh, S.Jl);
   const int k = f.k;
   project(S.W, S.Y0, S.P, R, C, k, sh);
   for (int idx = threadIdx.x; idx < k * R; idx += NT) {
@@ -866,12 +1038,11 @@ __device__ void two_site(const Slot& S, int i, bool right, bool is_swap, Shared&
           o = cconj(o);
         }
         S.Y0[at] = o;
-        S.W[at] = o;
       }
     }
   }
   __syncthreads();
-  const Factor f = factorise<RPL>(S.W, R, C, (int)S.chi, S.cutoff, true, sh, S.Jl);
+  const Factor f = factorise<RPL>(S.W, S.Y0, S.P, R, C, (int)S.chi, S.cutoff, true, sh, S.Jl);
   const int k = f.k;
   project(S.W, S.Y0, S.P, R, C, k, sh);
   if (right) {

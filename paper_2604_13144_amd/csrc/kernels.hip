@@ -639,6 +639,76 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
   return -1;
 }
 
+// ------------------------------------------------------- complex GEMM
+// C = A B for complex128 operands given by element accessors fa(i, k),
+// fb(k, j) and a store fc(i, j, value), on FP64 matrix cores.  Each wave owns
+// 32 x 32 output tiles (2 x 2 blocks of 16 x 16) and walks K in chunks of 8,
+// issuing the chunk's operand loads before its MFMAs.  A complex product
+// takes four real v_mfma_f64_16x16x4: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.
+// Operand layout of v_mfma_f64_16x16x4 (lane l): A[l % 16][l / 16],
+// B[l / 16][l % 16]; the accumulator holds D[l / 16 + 4 r][l % 16], r < 4.
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <typename FA, typename FB, typename FC>
+__device__ __forceinline__ void zgemm(int M, int N, int K, const FA& fa, const FB& fb,
+                                      const FC& fc) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tm = (M + 31) >> 5, tn = (N + 31) >> 5;
+#pragma unroll 1
+  for (int t = wv; t < tm * tn; t += NW) {
+    const int i0 = (t / tn) * 32, j0 = (t - (t / tn) * tn) * 32;
+    d4 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cr[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        ci[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+      }
+#pragma unroll 1
+    for (int k0 = 0; k0 < K; k0 += 8) {
+      z2 av[2][2], bv[2][2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int k = k0 + 4 * s + lk;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int i = i0 + 16 * q + li, j = j0 + 16 * q + li;
+          av[s][q] = (i < M && k < K) ? fa(i, k) : cmk(0.0, 0.0);
+          bv[s][q] = (j < N && k < K) ? fb(k, j) : cmk(0.0, 0.0);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][a].x, bv[s][b].x, cr[a][b], 0, 0, 0);
+            ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][a].x, bv[s][b].y, ci[a][b], 0, 0, 0);
+          }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[s][a].y, bv[s][b].y, cr[a][b], 0, 0, 0);
+            ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][a].y, bv[s][b].x, ci[a][b], 0, 0, 0);
+          }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + 16 * a + lk + 4 * r, j = j0 + 16 * b + li;
+          if (i < M && j < N) fc(i, j, cmk(cr[a][b][r], ci[a][b][r]));
+        }
+  }
+}
+
 // ------------------------------------------------- QR preconditioning
 // Householder QR with column pivoting of Z (nr x nc, column-major, global):
 // Z P = Q Rz.  On return the upper trapezoid of Z holds Rz and sh.piv[j] is
@@ -881,15 +951,13 @@ __device__ Factor factorise(z2* W, const z2* Y0, z2* X, int R, int C_, int cap, 
 // column perm[j] of W normalised to unit length.
 __device__ void project(const z2* W, const z2* Y0, z2* P, int R, int C, int k,
                         Shared& sh) {
-  for (int idx = threadIdx.x; idx < k * C; idx += NT) {
-    const int j = idx / C, col = idx - j * C;
-    const int pj = sh.perm[j];
-    const z2* w = W + (uint64_t)pj * R;
-    const z2* y = Y0 + (uint64_t)col * R;
-    z2 acc = cmk(0.0, 0.0);
-    for (int r = 0; r < R; ++r) cfmac(acc, w[r], y[r]);
-    P[idx] = cscale(acc, 1.0 / sqrt(sh.sig2[pj]));
-  }
+  const gz2* w = (const gz2*)W;
+  const gz2* y = (const gz2*)Y0;
+  gz2* out = (gz2*)P;
+  zgemm(k, C, R,
+        [&](int j, int r) { return cconj((z2)w[(uint64_t)sh.perm[j] * R + r]); },
+        [&](int r, int col) { return (z2)y[(uint64_t)col * R + r]; },
+        [&](int j, int col, z2 v) { out[(uint64_t)j * C + col] = cscale(v, rsq_nr(sh.sig2[sh.perm[j]])); });
   __syncthreads();
 }
 

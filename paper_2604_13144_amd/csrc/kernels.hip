@@ -1004,11 +1004,13 @@ __device__ void shift_right(const Slot& S, int c, double cutoff, Shared& sh) {
   // B' = P . B  (k x cr) . (cr x 2 cr2) into W, then back
   __syncthreads();
   const int nb = 2 * cr2;
-  for (int idx = threadIdx.x; idx < k * nb; idx += NT) {
-    const int j = idx / nb, col = idx - j * nb;
-    z2 acc = cmk(0.0, 0.0);
-    for (int b = 0; b < cr; ++b) cfma(acc, S.P[j * C + b], B[(uint64_t)b * nb + col]);
-    S.W[idx] = acc;
+  {
+    const gz2* pp = (const gz2*)S.P;
+    const gz2* bb = (const gz2*)B;
+    gz2* ww = (gz2*)S.W;
+    zgemm(k, nb, cr, [&](int j, int b) { return (z2)pp[(uint64_t)j * C + b]; },
+          [&](int b, int col) { return (z2)bb[(uint64_t)b * nb + col]; },
+          [&](int j, int col, z2 v) { ww[(uint64_t)j * nb + col] = v; });
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < k * nb; idx += NT) B[idx] = S.W[idx];
@@ -1042,11 +1044,13 @@ __device__ void shift_left(const Slot& S, int c, double cutoff, Shared& sh) {
   __syncthreads();
   // B' [x, s, j] = sum_a B[x, s, a] conj(P[j, a])
   const int nrow = 2 * cl0;
-  for (int idx = threadIdx.x; idx < nrow * k; idx += NT) {
-    const int xs = idx / k, j = idx - xs * k;
-    z2 acc = cmk(0.0, 0.0);
-    for (int a = 0; a < cl; ++a) cfma(acc, B[(uint64_t)xs * cl + a], cconj(S.P[j * C + a]));
-    S.W[idx] = acc;
+  {
+    const gz2* pp = (const gz2*)S.P;
+    const gz2* bb = (const gz2*)B;
+    gz2* ww = (gz2*)S.W;
+    zgemm(nrow, k, cl, [&](int xs, int a) { return (z2)bb[(uint64_t)xs * cl + a]; },
+          [&](int a, int j) { return cconj((z2)pp[(uint64_t)j * C + a]); },
+          [&](int xs, int j, z2 v) { ww[(uint64_t)xs * k + j] = v; });
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < nrow * k; idx += NT) B[idx] = S.W[idx];
@@ -1075,21 +1079,23 @@ __device__ void two_site(const Slot& S, int i, bool right, bool is_swap, Shared&
   const int cl = sh.bond[i], cm = sh.bond[i + 1], cr = sh.bond[i + 2];
   const int M = 2 * cl, N = 2 * cr;
   const int R = right ? M : N, C = right ? N : M;
-  // theta'[(a,u),(v,c)] = sum_{s,t} G[uv][st] sum_b A[a,s,b] B[b,t,c]
+  // theta[(a,s),(t,c)] = sum_b A[a,s,b] B[b,t,c] into W (row-major, M x N),
+  // then theta'[(a,u),(v,c)] = sum_{s,t} G[uv][st] theta[(a,s),(t,c)] into Y0
+  {
+    const gz2* aa = (const gz2*)A;
+    const gz2* bb = (const gz2*)B;
+    gz2* ww = (gz2*)S.W;
+    zgemm(M, N, cm, [&](int i, int b) { return (z2)aa[(uint64_t)i * cm + b]; },
+          [&](int b, int j) { return (z2)bb[(uint64_t)b * N + j]; },
+          [&](int i, int j, z2 v) { ww[(uint64_t)i * N + j] = v; });
+  }
+  __syncthreads();
   for (int idx = threadIdx.x; idx < cl * cr; idx += NT) {
     const int a = idx / cr, c = idx - a * cr;
-    z2 t00 = cmk(0, 0), t01 = cmk(0, 0), t10 = cmk(0, 0), t11 = cmk(0, 0);
-    const z2* a0 = A + (uint64_t)(a * 2 + 0) * cm;
-    const z2* a1 = A + (uint64_t)(a * 2 + 1) * cm;
-    for (int b = 0; b < cm; ++b) {
-      const z2 x0 = a0[b], x1 = a1[b];
-      const z2 y0 = B[(uint64_t)(b * 2 + 0) * cr + c], y1 = B[(uint64_t)(b * 2 + 1) * cr + c];
-      cfma(t00, x0, y0);
-      cfma(t01, x0, y1);
-      cfma(t10, x1, y0);
-      cfma(t11, x1, y1);
-    }
-    const z2 tv[4] = {t00, t01, t10, t11};
+    z2 tv[4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+      tv[st] = S.W[(uint64_t)(a * 2 + (st >> 1)) * N + (st & 1) * cr + c];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
 #pragma unroll

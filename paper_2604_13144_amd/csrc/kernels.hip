@@ -41,6 +41,19 @@ struct JCfg {
   static constexpr int LR = 16 * E + 1;                // LDS column stride (padded)
 };
 
+// LDS staging block size (complex elements) that serves the Jacobi of every
+// row class up to RPL (a launch runs smaller matrices with smaller E).
+template <int RPL>
+constexpr int jl_size() {
+  constexpr int own = JCfg<RPL>::JB * JCfg<RPL>::LR;
+  if constexpr (RPL > 1) {
+    constexpr int half = jl_size<RPL / 2>();
+    return own > half ? own : half;
+  } else {
+    return own;
+  }
+}
+
 // ---------------------------------------------------------------- complex
 // complex128 as a native two-lane vector (loads/stores of 16 bytes), with
 // pointer types that pin LDS (ds_*) and global (global_*) address spaces.
@@ -329,23 +342,23 @@ constexpr double kNormRecompute = 0.25;
 // of the column x in registers (element e of lane l is matrix row l + 16 e)
 // with its squared norm al; the partner column y is read from LDS once and
 // held in registers between the inner product and the update, and its
-// squared norm lives in LDS at yn.  Only the first ea = ceil(R / 16)
-// elements are touched (a wave-uniform bound).  Rows that are inactive or
+// squared norm lives in LDS at yn.  All E elements are processed without
+// per-element conditions (matrix rows beyond R are zero in registers and in
+// LDS and stay zero), so the element loop is straight-line code that the
+// compiler can interleave.  Rows that are inactive or
 // already orthogonal to tolerance leave both columns untouched.  Returns
 // |t| = |tan| of the rotation angle, or -1 when this row did not rotate.
 template <int E>
-__device__ __forceinline__ double rotate_rows(z2 (&x)[E], double& al, lz2* y, ld* yn, int ea,
-                                              int l16, bool active, double tiny, double tol2) {
+__device__ __forceinline__ double rotate_rows(z2 (&x)[E], double& al, lz2* y, ld* yn, int l16,
+                                              bool active, double tiny, double tol2) {
   double gr = 0.0, gi = 0.0;
   z2 yv[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    if (e < ea) {
-      const z2 b = y[l16 + 16 * e];
-      yv[e] = b;
-      gr = fma(x[e].x, b.x, fma(x[e].y, b.y, gr));
-      gi = fma(x[e].x, b.y, fma(-x[e].y, b.x, gi));
-    }
+    const z2 b = y[l16 + 16 * e];
+    yv[e] = b;
+    gr = fma(x[e].x, b.x, fma(x[e].y, b.y, gr));
+    gi = fma(x[e].x, b.y, fma(-x[e].y, b.x, gi));
   }
   gr = row16_sum(gr);
   gi = row16_sum(gi);
@@ -358,10 +371,8 @@ __device__ __forceinline__ double rotate_rows(z2 (&x)[E], double& al, lz2* y, ld
     tabs = fabs(r.t);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      if (e < ea) {
-        rot_apply(r, x[e], yv[e]);
-        y[l16 + 16 * e] = yv[e];
-      }
+      rot_apply(r, x[e], yv[e]);
+      y[l16 + 16 * e] = yv[e];
     }
     double an = al - r.tg, bn = be + r.tg;
     if (an < kNormRecompute * al) {
@@ -373,8 +384,7 @@ __device__ __forceinline__ double rotate_rows(z2 (&x)[E], double& al, lz2* y, ld
     if (bn < kNormRecompute * be) {
       double a = 0.0;
 #pragma unroll
-      for (int e = 0; e < E; ++e)
-        if (e < ea) a = fma(yv[e].x, yv[e].x, fma(yv[e].y, yv[e].y, a));
+      for (int e = 0; e < E; ++e) a = fma(yv[e].x, yv[e].x, fma(yv[e].y, yv[e].y, a));
       bn = row16_sum(a);
     }
     al = an;
@@ -390,19 +400,14 @@ __device__ __forceinline__ double rotate_rows(z2 (&x)[E], double& al, lz2* y, ld
 // at pn and qn; the part-0 row writes their updates.
 template <int EG, int G>
 __device__ __forceinline__ double rotate_split(lz2* xp, lz2* yq, ld* pn, ld* qn, int e0,
-                                               int ea, int l16, bool first, bool active,
+                                               int l16, bool first, bool active,
                                                double tiny, double tol2) {
   z2 xv[EG], yv[EG];
   double gr = 0.0, gi = 0.0;
 #pragma unroll
   for (int e = 0; e < EG; ++e) {
-    if (e0 + e < ea) {
-      xv[e] = xp[l16 + 16 * (e0 + e)];
-      yv[e] = yq[l16 + 16 * (e0 + e)];
-    } else {
-      xv[e] = cmk(0.0, 0.0);
-      yv[e] = cmk(0.0, 0.0);
-    }
+    xv[e] = xp[l16 + 16 * (e0 + e)];
+    yv[e] = yq[l16 + 16 * (e0 + e)];
     gr = fma(xv[e].x, yv[e].x, fma(xv[e].y, yv[e].y, gr));
     gi = fma(xv[e].x, yv[e].y, fma(-xv[e].y, yv[e].x, gi));
   }
@@ -418,10 +423,8 @@ __device__ __forceinline__ double rotate_split(lz2* xp, lz2* yq, ld* pn, ld* qn,
 #pragma unroll
     for (int e = 0; e < EG; ++e) {
       rot_apply(r, xv[e], yv[e]);
-      if (e0 + e < ea) {
-        xp[l16 + 16 * (e0 + e)] = xv[e];
-        yq[l16 + 16 * (e0 + e)] = yv[e];
-      }
+      xp[l16 + 16 * (e0 + e)] = xv[e];
+      yq[l16 + 16 * (e0 + e)] = yv[e];
     }
     double an = al - r.tg, bn = be + r.tg;
     if (an < kNormRecompute * al) {
@@ -445,13 +448,14 @@ __device__ __forceinline__ double rotate_split(lz2* xp, lz2* yq, ld* pn, ld* qn,
 }
 
 // Column <-> row registers.  From/to global memory only rows < R exist; the
-// register (and LDS) copies are zero-padded to a multiple of 16 rows.
+// register (and LDS) copies are zero-padded to 16 E rows.
 template <int E>
 __device__ __forceinline__ void row_load_g(z2 (&x)[E], const gz2* col, int R, int l16) {
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int r = l16 + 16 * e;
-    x[e] = r < R ? col[r] : cmk(0.0, 0.0);
+    const z2 v = col[r < R ? r : R - 1];     // in-bounds load, no branch
+    x[e] = r < R ? v : cmk(0.0, 0.0);
   }
 }
 
@@ -465,16 +469,15 @@ __device__ __forceinline__ void row_store_g(const z2 (&x)[E], gz2* col, int R, i
 }
 
 template <int E>
-__device__ __forceinline__ void row_load_l(z2 (&x)[E], const lz2* col, int ea, int l16) {
+__device__ __forceinline__ void row_load_l(z2 (&x)[E], const lz2* col, int l16) {
 #pragma unroll
-  for (int e = 0; e < E; ++e) x[e] = e < ea ? col[l16 + 16 * e] : cmk(0.0, 0.0);
+  for (int e = 0; e < E; ++e) x[e] = col[l16 + 16 * e];
 }
 
 template <int E>
-__device__ __forceinline__ void row_store_l(const z2 (&x)[E], lz2* col, int ea, int l16) {
+__device__ __forceinline__ void row_store_l(const z2 (&x)[E], lz2* col, int l16) {
 #pragma unroll
-  for (int e = 0; e < E; ++e)
-    if (e < ea) col[l16 + 16 * e] = x[e];
+  for (int e = 0; e < E; ++e) col[l16 + 16 * e] = x[e];
 }
 
 template <int E>
@@ -497,7 +500,6 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
   lz2* Jl = (lz2*)Jl_;
   ld* jn = (ld*)sh.jn;
   const int l16 = threadIdx.x & 15, row = threadIdx.x >> 4;
-  const int ea = (R + 15) >> 4;
   if (C < 2) return 0;
   // column norms (also the first sweep's ordering) and ||W||_F^2
 #pragma unroll 1
@@ -557,7 +559,7 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
 #pragma unroll
             for (int e = 0; e < E; ++e) y[e] = cmk(0.0, 0.0);
           }
-          row_store_l<E>(y, Jl + row * LR, ea, l16);
+          row_store_l<E>(y, Jl + row * LR, l16);
           const double b = row_norm2<E>(y);
           if (l16 == 0) jn[row] = b;
         }
@@ -577,7 +579,7 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
             for (int r = 0; r < 4; ++r) {
               const int jj = 4 * tb + ((r4 + r) & 3);
               const bool act = ai && J * JB + jj < C;
-              tmx = fmax(tmx, rotate_rows<E>(xi, al, Jl + jj * LR, jn + jj, ea, l16, act, tiny, tol2));
+              tmx = fmax(tmx, rotate_rows<E>(xi, al, Jl + jj * LR, jn + jj, l16, act, tiny, tol2));
               __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
             }
           }
@@ -585,7 +587,7 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
         }
         if (row < JB && J * JB + row < C) {
           z2 y[E];
-          row_load_l<E>(y, Jl + row * LR, ea, l16);
+          row_load_l<E>(y, Jl + row * LR, l16);
           row_store_g<E>(y, W + (uint64_t)sh.order[J * JB + row] * R, R, l16);
         }
         __syncthreads();
@@ -594,7 +596,7 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
       // of the JB/2 pairs of a round is shared by G rows of one wave, so
       // every row of the workgroup works
       if (row < JB) {
-        row_store_l<E>(xi, Jl + row * LR, ea, l16);
+        row_store_l<E>(xi, Jl + row * LR, l16);
         if (l16 == 0) jn[row] = al;
       }
       __syncthreads();
@@ -607,14 +609,14 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
           rr_pair(round, k, JB, p, q);
           const bool act = I * JB + q < C;
           tmx = fmax(tmx, rotate_split<EG, G>(Jl + p * LR, Jl + q * LR, jn + p, jn + q, h * EG,
-                                               ea, l16, h == 0, act, tiny, tol2));
+                                               l16, h == 0, act, tiny, tol2));
           __syncthreads();
         }
       }
       // write block I back and record its final column norms for the next order
       if (ai) {
         z2 x[E];
-        row_load_l<E>(x, Jl + row * LR, ea, l16);
+        row_load_l<E>(x, Jl + row * LR, l16);
         row_store_g<E>(x, W + (uint64_t)ci * R, R, l16);
         const double a = row_norm2<E>(x);
         if (l16 == 0) sh.sig2[ci] = a;
@@ -848,6 +850,16 @@ __device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_) {
   }
 }
 
+// Jacobi with the smallest row class that holds R rows (the element loops
+// run over all E = 4 RPL elements of a lane, so a smaller class saves work).
+template <int RPL>
+__device__ int jacobi_fit(z2* X, int R, int C, Shared& sh, z2* Jl) {
+  if constexpr (RPL > 1) {
+    if (R <= 32 * RPL) return jacobi_fit<RPL / 2>(X, R, C, sh, Jl);
+  }
+  return jacobi<RPL>(X, R, C, sh, Jl);
+}
+
 // Left singular vectors of M (R x C, column-major in Y0): Z = M^H is
 // factored as Z P = Q Rz (in W), one-sided Jacobi orthogonalises the m
 // columns of X = Rz^H (R x m, m = min(R, C), in the buffer X), and since
@@ -870,7 +882,7 @@ __device__ int svd_cols(z2* W, const z2* Y0, z2* X, int R, int C, Shared& sh, z2
     X[idx] = jj <= r ? cconj(W[(uint64_t)r * C + jj]) : cmk(0.0, 0.0);
   }
   __syncthreads();
-  const int sweeps = jacobi<RPL>(X, R, m, sh, Jl);
+  const int sweeps = jacobi_fit<RPL>(X, R, m, sh, Jl);
   for (int idx = threadIdx.x; idx < R * m; idx += NT) {
     const int jj = idx / R, r = idx - jj * R;
     W[(uint64_t)jj * R + sh.piv[r]] = X[idx];
@@ -1409,7 +1421,7 @@ __global__ __launch_bounds__(NT) void init_kernel(EngineArgs a) {
 template <int RPL>
 __global__ __launch_bounds__(NT) void evolve_kernel(EngineArgs a, uint32_t n_layers) {
   __shared__ Shared sh;
-  __shared__ z2 Jl[JCfg<RPL>::JB * JCfg<RPL>::LR];
+  __shared__ z2 Jl[jl_size<RPL>()];
   const int slot = blockIdx.x;
   const Slot S = make_slot(a, slot, Jl);
   load_state(a, slot, sh);
@@ -1451,7 +1463,7 @@ template <int RPL>
 __global__ __launch_bounds__(NT) void observe_kernel(EngineArgs a, double* values,
                                                      double* weights) {
   __shared__ Shared sh;
-  __shared__ z2 Jl[JCfg<RPL>::JB * JCfg<RPL>::LR];
+  __shared__ z2 Jl[jl_size<RPL>()];
   __shared__ double acc_obs[256];
   const int slot = blockIdx.x;
   const Slot S = make_slot(a, slot, Jl);

@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "TEPAI_OK", -1: "TEPAI_EINVAL", -2: "TEPAI_ERANGE", -3: "TEPA
                 -4: "TEPAI_EDEVICE", -5: "TEPAI_ENUMERIC"}
 PAULI_CODE = {"X": 1, "Y": 2, "Z": 3}
 TEPAI_FP64 = 0
+TEPAI_FP32_MIXED = 1
 
 
 class tepai_term(C.Structure):
@@ -125,7 +126,8 @@ def _ptr(a: np.ndarray):
 class ProblemStruct:
     """A tepai_problem plus the host arrays it points to (kept alive here)."""
 
-    def __init__(self, problem, chi_per_sample: Optional[Sequence[int]] = None):
+    def __init__(self, problem, chi_per_sample: Optional[Sequence[int]] = None,
+                 precision: int = TEPAI_FP64):
         p = problem
         if len(p.initial_bits) != p.n_qubits:
             raise ValueError("initial_bits must hold one character per qubit")
@@ -174,7 +176,7 @@ class ProblemStruct:
         s.n_obs = len(p.observables)
         s.n_strings = len(strings)
         s.strings = C.cast(self._strings, C.POINTER(tepai_pauli_string))
-        s.precision = TEPAI_FP64
+        s.precision = int(precision)
         s.flags = 0
         self.struct = s
         self.n_obs = s.n_obs

@@ -161,7 +161,8 @@ tepai_status validate(tepai_handle* h, const tepai_problem* p) {
     }
     if (!std::isfinite(ps.coeff)) return fail(h, TEPAI_ERANGE, "non-finite string coefficient");
   }
-  if (p->precision != TEPAI_FP64) return fail(h, TEPAI_EINVAL, "unsupported precision");
+  if (p->precision != TEPAI_FP64 && p->precision != TEPAI_FP32_MIXED)
+    return fail(h, TEPAI_EINVAL, "unsupported precision");
   if (p->flags != 0) return fail(h, TEPAI_EINVAL, "unsupported flags");
   return TEPAI_OK;
 }
@@ -178,7 +179,9 @@ Layout layout(const tepai_problem& p, uint32_t l_eff, uint32_t count) {
   Layout L{};
   const uint64_t chi = p.chi_max;
   L.site_stride = 2 * chi * chi;
-  L.work_stride = 3 * (2 * chi) * (2 * chi);
+  // three scratch matrices of (2 chi)^2, each at least one element per
+  // thread (the QR's trailing pass parks out-of-column stores in the third)
+  L.work_stride = 3 * std::max<uint64_t>((2 * chi) * (2 * chi), kThreads);
   size_t off = 0;
   L.rows = off;
   off = align256(off + sizeof(DevRow) * l_eff);
@@ -191,7 +194,8 @@ Layout layout(const tepai_problem& p, uint32_t l_eff, uint32_t count) {
   L.states = off;
   off = align256(off + sizeof(SampleState) * count);
   L.tensors = off;
-  off = align256(off + sizeof(double2) * L.site_stride * p.n_qubits * count);
+  const size_t elem = p.precision == TEPAI_FP32_MIXED ? sizeof(float2) : sizeof(double2);
+  off = align256(off + elem * L.site_stride * p.n_qubits * count);
   L.work = off;
   off = align256(off + sizeof(double2) * L.work_stride * count);
   L.total = off;
@@ -380,7 +384,11 @@ tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_
   a.work_stride = lay.work_stride;
   a.first_sample = p->sample_offset + first;
   a.seed = p->seed;
-  a.cutoff = p->svd_cutoff;
+  a.mixed = p->precision == TEPAI_FP32_MIXED ? 1u : 0u;
+  // complex64 contractions leave rounding noise near 1e-8 sigma_0 in the
+  // spectrum; the mixed path does not count it as Schmidt rank
+  a.cutoff = a.mixed ? std::max(p->svd_cutoff, kCutoffMixed) : p->svd_cutoff;
+  a.stop_tan = a.mixed ? kStopTanMixed : kStopTanFp64;
   a.log_g1_step = t.log_step;
   a.l_eff = L;
   a.n = p->n_qubits;

@@ -21,6 +21,7 @@
 // The engine is instantiated for RPL = 1, 2, 4, 8 (matrices of up to 64 RPL
 // rows, i.e. chi_max <= 32 RPL), which sizes registers and LDS blocks.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include <cmath>
 #include <cstdint>
@@ -61,6 +62,10 @@ typedef double z2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) z2 lz2;
 typedef __attribute__((address_space(1))) z2 gz2;
 typedef __attribute__((address_space(3))) double ld;
+// complex64 storage of the mixed-precision path's site tensors
+typedef float f2 __attribute__((ext_vector_type(2)));
+template <typename T>
+using glob = __attribute__((address_space(1))) T;
 
 __device__ __forceinline__ z2 cmk(double r, double i) {
   z2 v;
@@ -74,6 +79,23 @@ __device__ __forceinline__ z2 cmul(z2 a, z2 b) {
 }
 __device__ __forceinline__ z2 cconj(z2 a) { return cmk(a.x, -a.y); }
 __device__ __forceinline__ z2 cscale(z2 a, double s) { return cmk(a.x * s, a.y * s); }
+
+// Site-tensor element type: complex128, or complex64 on the mixed path.
+template <bool MIX>
+using TSite = typename std::conditional<MIX, f2, z2>::type;
+__device__ __forceinline__ z2 toz(z2 v) { return v; }
+__device__ __forceinline__ z2 toz(f2 v) { return cmk((double)v.x, (double)v.y); }
+template <typename T>
+__device__ __forceinline__ T fromz(z2 v);
+template <>
+__device__ __forceinline__ z2 fromz<z2>(z2 v) { return v; }
+template <>
+__device__ __forceinline__ f2 fromz<f2>(z2 v) {
+  f2 r;
+  r.x = (float)v.x;
+  r.y = (float)v.y;
+  return r;
+}
 // acc += a * b
 __device__ __forceinline__ void cfma(z2& acc, z2 a, z2 b) {
   acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
@@ -233,18 +255,20 @@ struct Shared {
 };
 
 struct Slot {
-  z2* T;      // site tensors of this sample
+  void* T;   // site tensors of this sample (z2, or f2 on the mixed path)
   z2* Y0;     // scratch: factorised matrix (kept)
   z2* W;      // scratch: Jacobi working copy
   z2* P;      // scratch: projections
   z2* Jl;     // LDS staging block of the Jacobi sweeps
   uint64_t ss;     // site stride
+  double stop;       // Jacobi stops after a sweep whose |tan| <= stop
   double cutoff;
   uint32_t chi;
   uint32_t n;
 };
 
-__device__ __forceinline__ z2* site(const Slot& s, int k) { return s.T + (uint64_t)k * s.ss; }
+template <typename TS>
+__device__ __forceinline__ TS* site(const Slot& s, int k) { return (TS*)s.T + (uint64_t)k * s.ss; }
 
 __device__ double svd_flops(double m, double n) {
   if (m < n) {
@@ -307,7 +331,7 @@ __device__ __forceinline__ double rows_sum(double v) {
 // |y'|^2 = beta + t|gamma| (the two-sided Jacobi update of the 2 x 2 Gram
 // matrix).
 struct Rot {
-  double c, s, er, ei, t, tg;
+  double c, sr, si, t, tg;   // cosine, s e^{i phi} = sr + i si, tan, t |gamma|
 };
 
 __device__ __forceinline__ Rot rot_params(double al, double be, double gr, double gi, double g2) {
@@ -318,19 +342,19 @@ __device__ __forceinline__ Rot rot_params(double al, double be, double gr, doubl
   const double hq = q * rsq_nr(q);
   r.t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(zeta) + hq);
   r.c = rsq_nr(1.0 + r.t * r.t);
-  r.s = r.c * r.t;
-  r.er = gr * ig;
-  r.ei = gi * ig;
+  const double s = r.c * r.t;
+  r.sr = s * (gr * ig);
+  r.si = s * (gi * ig);
   r.tg = r.t * (g2 * ig);
   return r;
 }
 
+// x <- c x - conj(s e^{i phi}) y, y <- (s e^{i phi}) x + c y: three real
+// multiply-adds per output component.
 __device__ __forceinline__ void rot_apply(const Rot& r, z2& a, z2& b) {
   const z2 x = a, y = b;
-  const z2 eb = cmk(r.er * y.x + r.ei * y.y, r.er * y.y - r.ei * y.x);   // e^{-i phi} y
-  const z2 ex = cmk(r.er * x.x - r.ei * x.y, r.er * x.y + r.ei * x.x);   // e^{i phi} x
-  a = cmk(r.c * x.x - r.s * eb.x, r.c * x.y - r.s * eb.y);
-  b = cmk(r.s * ex.x + r.c * y.x, r.s * ex.y + r.c * y.y);
+  a = cmk(fma(-r.si, y.y, fma(-r.sr, y.x, r.c * x.x)), fma(r.si, y.x, fma(-r.sr, y.y, r.c * x.y)));
+  b = cmk(fma(-r.si, x.y, fma(r.sr, x.x, r.c * y.x)), fma(r.si, x.x, fma(r.sr, x.y, r.c * y.y)));
 }
 
 // A squared norm carried through rotations by the update above loses
@@ -493,7 +517,7 @@ __device__ __forceinline__ double row_norm2(const z2 (&x)[E]) {
 // staging block (JB columns).  Returns the number of sweeps, or -1 when the
 // sweep cap was reached.
 template <int RPL>
-__device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
+__device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_, double stop) {
   using K = JCfg<RPL>;
   constexpr int E = K::E, JB = K::JB, LR = K::LR;
   gz2* W = (gz2*)W_;
@@ -624,9 +648,10 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
       __syncthreads();
     }
     // Stop when no pair rotated, or when every rotation of this sweep turned
-    // by |tan| <= 1e-8: the columns then moved by at most 1e-8 of their
-    // partners, so the non-orthogonality left behind is ~1e-16 and a further
-    // sweep would find nothing above the tolerance.
+    // by |tan| <= stop: the columns then moved by at most `stop` of their
+    // partners, so the non-orthogonality left behind is ~stop^2 (1e-16 at the
+    // FP64 path's 1e-8, where a further sweep would find nothing above the
+    // tolerance).
     tmx = wave_max(tmx);
     if ((threadIdx.x & 63) == 0 && tmx >= 0.0) {
       sh.flag = 1;
@@ -636,7 +661,7 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_) {
     const int rotated = sh.flag;
     const double tm = sh.tmax;
     __syncthreads();
-    if (!rotated || tm <= 1e-8) return sweep;
+    if (!rotated || tm <= stop) return sweep;
   }
   return -1;
 }
@@ -711,6 +736,82 @@ __device__ __forceinline__ void zgemm(int M, int N, int K, const FA& fa, const F
   }
 }
 
+// The same product on FP32 matrix cores (mixed path): operands rounded to
+// complex64, FP32 accumulation (v_mfma_f32_16x16x4f32, lane layout as above
+// for A and B; the accumulator holds D[4 (l / 16) + r][l % 16], r < 4).
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename FA, typename FB, typename FC>
+__device__ __forceinline__ void zgemm32(int M, int N, int K, const FA& fa, const FB& fb,
+                                        const FC& fc) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tm = (M + 31) >> 5, tn = (N + 31) >> 5;
+#pragma unroll 1
+  for (int t = wv; t < tm * tn; t += NW) {
+    const int i0 = (t / tn) * 32, j0 = (t - (t / tn) * tn) * 32;
+    f4 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cr[a][b] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        ci[a][b] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+      }
+#pragma unroll 1
+    for (int k0 = 0; k0 < K; k0 += 8) {
+      f2 av[2][2], bv[2][2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int k = k0 + 4 * s + lk;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int i = i0 + 16 * q + li, j = j0 + 16 * q + li;
+          av[s][q] = fromz<f2>((i < M && k < K) ? fa(i, k) : cmk(0.0, 0.0));
+          bv[s][q] = fromz<f2>((j < N && k < K) ? fb(k, j) : cmk(0.0, 0.0));
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            cr[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s][a].x, bv[s][b].x, cr[a][b], 0, 0, 0);
+            ci[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s][a].x, bv[s][b].y, ci[a][b], 0, 0, 0);
+          }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            cr[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-av[s][a].y, bv[s][b].y, cr[a][b], 0, 0, 0);
+            ci[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s][a].y, bv[s][b].x, ci[a][b], 0, 0, 0);
+          }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + 16 * a + 4 * lk + r, j = j0 + 16 * b + li;
+          if (i < M && j < N) fc(i, j, cmk((double)cr[a][b][r], (double)ci[a][b][r]));
+        }
+  }
+}
+
+// Contraction on the path's matrix cores: FP64, or FP32 on the mixed path.
+template <bool MIX, typename FA, typename FB, typename FC>
+__device__ __forceinline__ void zgemm_p(int M, int N, int K, const FA& fa, const FB& fb,
+                                        const FC& fc) {
+  if constexpr (MIX) {
+    zgemm32(M, N, K, fa, fb, fc);
+  } else {
+    zgemm(M, N, K, fa, fb, fc);
+  }
+}
+
 // ------------------------------------------------- QR preconditioning
 // Householder QR with column pivoting of Z (nr x nc, column-major, global):
 // Z P = Q Rz.  On return the upper trapezoid of Z holds Rz and sh.piv[j] is
@@ -722,10 +823,10 @@ __device__ __forceinline__ void zgemm(int M, int N, int K, const FA& fa, const F
 // x = Z[j:, j], x_0 = |x_0| e^{i phi}: beta = -e^{i phi} |x|, u = x - beta e_0,
 // H = I - kappa u u^H with kappa = 1 / (|x| (|x| + |x_0|)); H is unitary and
 // Hermitian and maps x to beta e_0, so H y = y - kappa (u^H y) u.
-template <int RPL>
-__device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_) {
+template <int RPL, typename TZ>
+__device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_, z2* dummy_) {
   constexpr int E = 4 * RPL;
-  gz2* Z = (gz2*)Z_;
+  glob<TZ>* Z = (glob<TZ>*)Z_;
   lz2* Ul = (lz2*)Ul_;
   ld* vn = (ld*)sh.sig2;
   const int l16 = threadIdx.x & 15, row = threadIdx.x >> 4;
@@ -733,13 +834,13 @@ __device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_) {
   const int eall = (nr + 15) >> 4;
 #pragma unroll 1
   for (int i = row; i < nc; i += NROWS) {
-    const gz2* col = Z + (uint64_t)i * nr;
+    const glob<TZ>* col = Z + (uint64_t)i * nr;
     double a = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int r = l16 + 16 * e;
       if (e < eall && r < nr) {
-        const z2 v = col[r];
+        const z2 v = toz((TZ)col[r]);
         a = fma(v.x, v.x, fma(v.y, v.y, a));
       }
     }
@@ -779,10 +880,10 @@ __device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_) {
     const int p = sh.qr_p;
     if (!(sh.qr_v > 0.0)) break;      // every remaining column is zero
     if (p != j) {
-      gz2* a = Z + (uint64_t)j * nr;
-      gz2* b = Z + (uint64_t)p * nr;
+      glob<TZ>* a = Z + (uint64_t)j * nr;
+      glob<TZ>* b = Z + (uint64_t)p * nr;
       for (int r = threadIdx.x; r < nr; r += NT) {
-        const z2 t = a[r];
+        const TZ t = a[r];
         a[r] = b[r];
         b[r] = t;
       }
@@ -797,50 +898,70 @@ __device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_) {
     }
     __syncthreads();
     if (wv == 0) {
-      gz2* col = Z + (uint64_t)j * nr;
-      const z2 a0 = col[j];
+      glob<TZ>* col = Z + (uint64_t)j * nr;
+      const z2 a0 = toz((TZ)col[j]);
       const double aa = sqrt(a0.x * a0.x + a0.y * a0.y);
       const double xn = sqrt(vn[j]);
       const z2 ph = aa > 0.0 ? cmk(a0.x / aa, a0.y / aa) : cmk(1.0, 0.0);
       for (int r = j + lane; r < nr; r += 64)
-        Ul[r] = r == j ? cmk(ph.x * (aa + xn), ph.y * (aa + xn)) : col[r];
+        Ul[r] = r == j ? cmk(ph.x * (aa + xn), ph.y * (aa + xn)) : toz((TZ)col[r]);
       if (lane == 0) {
-        col[j] = cmk(-ph.x * xn, -ph.y * xn);
+        col[j] = fromz<TZ>(cmk(-ph.x * xn, -ph.y * xn));
         sh.qr_k = 1.0 / (xn * (xn + aa));
       }
     }
     __syncthreads();
     const double kap = sh.qr_k;
+    // elements e < ea of a lane hold rows j + l16 + 16 e < nr; the passes run
+    // over groups of four elements behind a uniform bound, with in-bounds
+    // (clamped) loads and stores past the column sent to a per-lane dummy
+    // slot, so each group is straight-line code
     const int ea = (nr - j + 15) >> 4;
     z2 uv[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int r = j + l16 + 16 * e;
-      uv[e] = (e < ea && r < nr) ? (z2)Ul[r] : cmk(0.0, 0.0);
+    for (int g = 0; g < E / 4; ++g) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = 4 * g + q, r = j + l16 + 16 * e;
+        const z2 u = (4 * g < ea) ? (z2)Ul[r < nr ? r : nr - 1] : cmk(0.0, 0.0);
+        uv[e] = r < nr ? u : cmk(0.0, 0.0);
+      }
     }
+    glob<TZ>* dummy = (glob<TZ>*)dummy_ + threadIdx.x;
 #pragma unroll 1
     for (int i = j + 1 + row; i < nc; i += NROWS) {
-      gz2* col = Z + (uint64_t)i * nr;
+      glob<TZ>* col = Z + (uint64_t)i * nr;
       z2 z[E];
       double gr = 0.0, gi = 0.0;
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int r = j + l16 + 16 * e;
-        z[e] = (e < ea && r < nr) ? (z2)col[r] : cmk(0.0, 0.0);
-        gr = fma(uv[e].x, z[e].x, fma(uv[e].y, z[e].y, gr));
-        gi = fma(uv[e].x, z[e].y, fma(-uv[e].y, z[e].x, gi));
+      for (int g = 0; g < E / 4; ++g) {
+        if (4 * g < ea) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int e = 4 * g + q, r = j + l16 + 16 * e;
+            const z2 v = toz((TZ)col[r < nr ? r : nr - 1]);
+            z[e] = r < nr ? v : cmk(0.0, 0.0);
+            gr = fma(uv[e].x, z[e].x, fma(uv[e].y, z[e].y, gr));
+            gi = fma(uv[e].x, z[e].y, fma(-uv[e].y, z[e].x, gi));
+          }
+        }
       }
       gr = row16_sum(gr) * kap;
       gi = row16_sum(gi) * kap;
       double a = 0.0;
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int r = j + l16 + 16 * e;
-        if (e < ea && r < nr) {
-          const z2 u = uv[e];
-          const z2 v = cmk(z[e].x - (gr * u.x - gi * u.y), z[e].y - (gr * u.y + gi * u.x));
-          col[r] = v;
-          if (r > j) a = fma(v.x, v.x, fma(v.y, v.y, a));
+      for (int g = 0; g < E / 4; ++g) {
+        if (4 * g < ea) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int e = 4 * g + q, r = j + l16 + 16 * e;
+            const z2 u = uv[e];
+            const z2 v = cmk(z[e].x - (gr * u.x - gi * u.y), z[e].y - (gr * u.y + gi * u.x));
+            glob<TZ>* dst = r < nr ? col + r : dummy;
+            *dst = fromz<TZ>(v);
+            const double w = r > j ? 1.0 : 0.0;     // row j leaves the norm
+            a = fma(w * v.x, v.x, fma(w * v.y, v.y, a));
+          }
         }
       }
       a = row16_sum(a);
@@ -853,11 +974,11 @@ __device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_) {
 // Jacobi with the smallest row class that holds R rows (the element loops
 // run over all E = 4 RPL elements of a lane, so a smaller class saves work).
 template <int RPL>
-__device__ int jacobi_fit(z2* X, int R, int C, Shared& sh, z2* Jl) {
+__device__ int jacobi_fit(z2* X, int R, int C, Shared& sh, z2* Jl, double stop) {
   if constexpr (RPL > 1) {
-    if (R <= 32 * RPL) return jacobi_fit<RPL / 2>(X, R, C, sh, Jl);
+    if (R <= 32 * RPL) return jacobi_fit<RPL / 2>(X, R, C, sh, Jl, stop);
   }
-  return jacobi<RPL>(X, R, C, sh, Jl);
+  return jacobi<RPL>(X, R, C, sh, Jl, stop);
 }
 
 // Left singular vectors of M (R x C, column-major in Y0): Z = M^H is
@@ -868,21 +989,27 @@ __device__ int jacobi_fit(z2* X, int R, int C, Shared& sh, z2* Jl) {
 // (R x m, column-major).  The pivoted QR concentrates the norm in the leading
 // columns, which cuts the number of Jacobi sweeps (Drmac and Veselic's QR
 // preconditioning of one-sided Jacobi).  Returns the sweeps (-1 at the cap).
-template <int RPL>
-__device__ int svd_cols(z2* W, const z2* Y0, z2* X, int R, int C, Shared& sh, z2* Jl) {
+template <int RPL, bool MIX>
+__device__ int svd_cols(z2* W, const z2* Y0, z2* X, int R, int C, Shared& sh, z2* Jl,
+                         double stop) {
+  // the QR works on complex128 on both paths: its passes are bound by
+  // instruction issue, and complex64 storage costs more in conversions than
+  // it saves in bytes
+  using TZ = z2;
+  TZ* Z = (TZ*)W;
   for (int idx = threadIdx.x; idx < R * C; idx += NT) {
     const int c = idx / R, r = idx - c * R;
-    W[(uint64_t)r * C + c] = cconj(Y0[idx]);
+    Z[(uint64_t)r * C + c] = fromz<TZ>(cconj(Y0[idx]));
   }
   __syncthreads();
-  qrcp<RPL>(W, C, R, sh, Jl);
+  qrcp<RPL, TZ>(W, C, R, sh, Jl, X);      // X is free until the QR is done
   const int m = R < C ? R : C;
   for (int idx = threadIdx.x; idx < R * m; idx += NT) {
     const int jj = idx / R, r = idx - jj * R;
-    X[idx] = jj <= r ? cconj(W[(uint64_t)r * C + jj]) : cmk(0.0, 0.0);
+    X[idx] = jj <= r ? cconj(toz(Z[(uint64_t)r * C + jj])) : cmk(0.0, 0.0);
   }
   __syncthreads();
-  const int sweeps = jacobi_fit<RPL>(X, R, m, sh, Jl);
+  const int sweeps = jacobi_fit<RPL>(X, R, m, sh, Jl, stop);
   for (int idx = threadIdx.x; idx < R * m; idx += NT) {
     const int jj = idx / R, r = idx - jj * R;
     W[(uint64_t)jj * R + sh.piv[r]] = X[idx];
@@ -900,11 +1027,11 @@ struct Factor {
 // times the singular values (svd_cols, with X as scratch); sort, choose
 // k = min(cap, #{sigma > cutoff sigma_0}), record statistics.  sh.perm[j] is
 // the column of W holding the j-th largest sigma.
-template <int RPL>
+template <int RPL, bool MIX>
 __device__ Factor factorise(z2* W, const z2* Y0, z2* X, int R, int C_, int cap, double cutoff,
-                            bool record, Shared& sh, z2* Jl) {
+                            bool record, Shared& sh, z2* Jl, double stop) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int sweeps = svd_cols<RPL>(W, Y0, X, R, C_, sh, Jl);
+  const int sweeps = svd_cols<RPL, MIX>(W, Y0, X, R, C_, sh, Jl, stop);
   const int C = R < C_ ? R : C_;     // columns of W from here on
   for (int j = wv; j < C; j += NW) {
     const z2* w = W + (uint64_t)j * R;
@@ -961,12 +1088,13 @@ __device__ Factor factorise(z2* W, const z2* Y0, z2* X, int R, int C_, int cap, 
 
 // P[j][col] = sum_r conj(yhat_j[r]) Y0[col*R + r] for j < k, where yhat_j is
 // column perm[j] of W normalised to unit length.
+template <bool MIX>
 __device__ void project(const z2* W, const z2* Y0, z2* P, int R, int C, int k,
                         Shared& sh) {
   const gz2* w = (const gz2*)W;
   const gz2* y = (const gz2*)Y0;
   gz2* out = (gz2*)P;
-  zgemm(k, C, R,
+  zgemm_p<MIX>(k, C, R,
         [&](int j, int r) { return cconj((z2)w[(uint64_t)sh.perm[j] * R + r]); },
         [&](int r, int col) { return (z2)y[(uint64_t)col * R + r]; },
         [&](int j, int col, z2 v) { out[(uint64_t)j * C + col] = cscale(v, rsq_nr(sh.sig2[sh.perm[j]])); });
@@ -974,58 +1102,61 @@ __device__ void project(const z2* W, const z2* Y0, z2* P, int R, int C, int k,
 }
 
 // -------------------------------------------------------- MPS operations
+template <bool MIX>
 __device__ void apply_local(const Slot& S, int k, const z2 U[4], Shared& sh) {
-  z2* A = site(S, k);
+  using TS = TSite<MIX>;
+  TS* A = site<TS>(S, k);
   const int cl = sh.bond[k], cr = sh.bond[k + 1];
   for (int idx = threadIdx.x; idx < cl * cr; idx += NT) {
     const int a = idx / cr, b = idx - a * cr;
-    z2* x0 = A + (uint64_t)(a * 2 + 0) * cr + b;
-    z2* x1 = A + (uint64_t)(a * 2 + 1) * cr + b;
-    const z2 v0 = *x0, v1 = *x1;
+    TS* x0 = A + (uint64_t)(a * 2 + 0) * cr + b;
+    TS* x1 = A + (uint64_t)(a * 2 + 1) * cr + b;
+    const z2 v0 = toz(*x0), v1 = toz(*x1);
     z2 o0 = cmk(0.0, 0.0), o1 = cmk(0.0, 0.0);
     cfma(o0, U[0], v0);
     cfma(o0, U[1], v1);
     cfma(o1, U[2], v0);
     cfma(o1, U[3], v1);
-    *x0 = o0;
-    *x1 = o1;
+    *x0 = fromz<TS>(o0);
+    *x1 = fromz<TS>(o1);
   }
   __syncthreads();
 }
 
 // Move the centre from site c to c+1 (SVD of A_c as a (2 cl) x cr matrix).
-template <int RPL>
+template <int RPL, bool MIX>
 __device__ void shift_right(const Slot& S, int c, double cutoff, Shared& sh) {
-  z2* A = site(S, c);
-  z2* B = site(S, c + 1);
+  using TS = TSite<MIX>;
+  TS* A = site<TS>(S, c);
+  TS* B = site<TS>(S, c + 1);
   const int cl = sh.bond[c], cr = sh.bond[c + 1], cr2 = sh.bond[c + 2];
   const int R = 2 * cl, C = cr;
   for (int idx = threadIdx.x; idx < R * C; idx += NT) {
     const int row = idx / C, col = idx - row * C;
-    S.Y0[(uint64_t)col * R + row] = A[idx];
+    S.Y0[(uint64_t)col * R + row] = toz(A[idx]);
   }
   __syncthreads();
-  const Factor f = factorise<RPL>(S.W, S.Y0, S.P, R, C, C, cutoff, false, sh, S.Jl);
+  const Factor f = factorise<RPL, MIX>(S.W, S.Y0, S.P, R, C, C, cutoff, false, sh, S.Jl, S.stop);
   const int k = f.k;
-  project(S.W, S.Y0, S.P, R, C, k, sh);
+  project<MIX>(S.W, S.Y0, S.P, R, C, k, sh);
   for (int idx = threadIdx.x; idx < R * k; idx += NT) {
     const int row = idx / k, j = idx - row * k;
     const int pj = sh.perm[j];
-    A[idx] = cscale(S.W[(uint64_t)pj * R + row], 1.0 / sqrt(sh.sig2[pj]));
+    A[idx] = fromz<TS>(cscale(S.W[(uint64_t)pj * R + row], 1.0 / sqrt(sh.sig2[pj])));
   }
   // B' = P . B  (k x cr) . (cr x 2 cr2) into W, then back
   __syncthreads();
   const int nb = 2 * cr2;
   {
     const gz2* pp = (const gz2*)S.P;
-    const gz2* bb = (const gz2*)B;
+    const glob<TS>* bb = (const glob<TS>*)B;
     gz2* ww = (gz2*)S.W;
-    zgemm(k, nb, cr, [&](int j, int b) { return (z2)pp[(uint64_t)j * C + b]; },
-          [&](int b, int col) { return (z2)bb[(uint64_t)b * nb + col]; },
+    zgemm_p<MIX>(k, nb, cr, [&](int j, int b) { return (z2)pp[(uint64_t)j * C + b]; },
+          [&](int b, int col) { return toz((TS)bb[(uint64_t)b * nb + col]); },
           [&](int j, int col, z2 v) { ww[(uint64_t)j * nb + col] = v; });
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < k * nb; idx += NT) B[idx] = S.W[idx];
+  for (int idx = threadIdx.x; idx < k * nb; idx += NT) B[idx] = fromz<TS>(S.W[idx]);
   if (threadIdx.x == 0) {
     sh.bond[c + 1] = (uint16_t)k;
     sh.centre = c + 1;
@@ -1035,37 +1166,38 @@ __device__ void shift_right(const Slot& S, int c, double cutoff, Shared& sh) {
 }
 
 // Move the centre from site c to c-1 (SVD of A_c as a cl x (2 cr) matrix).
-template <int RPL>
+template <int RPL, bool MIX>
 __device__ void shift_left(const Slot& S, int c, double cutoff, Shared& sh) {
-  z2* A = site(S, c);
-  z2* B = site(S, c - 1);
+  using TS = TSite<MIX>;
+  TS* A = site<TS>(S, c);
+  TS* B = site<TS>(S, c - 1);
   const int cl = sh.bond[c], cr = sh.bond[c + 1], cl0 = sh.bond[c - 1];
   const int R = 2 * cr, C = cl;
   for (int idx = threadIdx.x; idx < R * C; idx += NT) {
-    S.Y0[idx] = cconj(A[idx]);      // Y = A^H, same memory order
+    S.Y0[idx] = cconj(toz(A[idx]));      // Y = A^H, same memory order
   }
   __syncthreads();
-  const Factor f = factorise<RPL>(S.W, S.Y0, S.P, R, C, C, cutoff, false, sh, S.Jl);
+  const Factor f = factorise<RPL, MIX>(S.W, S.Y0, S.P, R, C, C, cutoff, false, sh, S.Jl, S.stop);
   const int k = f.k;
-  project(S.W, S.Y0, S.P, R, C, k, sh);
+  project<MIX>(S.W, S.Y0, S.P, R, C, k, sh);
   for (int idx = threadIdx.x; idx < k * R; idx += NT) {
     const int j = idx / R, col = idx - j * R;
     const int pj = sh.perm[j];
-    A[idx] = cconj(cscale(S.W[(uint64_t)pj * R + col], 1.0 / sqrt(sh.sig2[pj])));
+    A[idx] = fromz<TS>(cconj(cscale(S.W[(uint64_t)pj * R + col], 1.0 / sqrt(sh.sig2[pj]))));
   }
   __syncthreads();
   // B' [x, s, j] = sum_a B[x, s, a] conj(P[j, a])
   const int nrow = 2 * cl0;
   {
     const gz2* pp = (const gz2*)S.P;
-    const gz2* bb = (const gz2*)B;
+    const glob<TS>* bb = (const glob<TS>*)B;
     gz2* ww = (gz2*)S.W;
-    zgemm(nrow, k, cl, [&](int xs, int a) { return (z2)bb[(uint64_t)xs * cl + a]; },
+    zgemm_p<MIX>(nrow, k, cl, [&](int xs, int a) { return toz((TS)bb[(uint64_t)xs * cl + a]); },
           [&](int a, int j) { return cconj((z2)pp[(uint64_t)j * C + a]); },
           [&](int xs, int j, z2 v) { ww[(uint64_t)xs * k + j] = v; });
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < nrow * k; idx += NT) B[idx] = S.W[idx];
+  for (int idx = threadIdx.x; idx < nrow * k; idx += NT) B[idx] = fromz<TS>(S.W[idx]);
   if (threadIdx.x == 0) {
     sh.bond[c] = (uint16_t)k;
     sh.centre = c - 1;
@@ -1074,31 +1206,32 @@ __device__ void shift_left(const Slot& S, int c, double cutoff, Shared& sh) {
   __syncthreads();
 }
 
-template <int RPL>
+template <int RPL, bool MIX>
 __device__ void move_centre_to(const Slot& S, int i, Shared& sh) {
-  while (sh.centre < i) shift_right<RPL>(S, sh.centre, S.cutoff, sh);
-  while (sh.centre > i + 1) shift_left<RPL>(S, sh.centre, S.cutoff, sh);
+  while (sh.centre < i) shift_right<RPL, MIX>(S, sh.centre, S.cutoff, sh);
+  while (sh.centre > i + 1) shift_left<RPL, MIX>(S, sh.centre, S.cutoff, sh);
 }
 
 // Truncated two-site update of sites (i, i+1) with operator G (site order,
 // index s_i * 2 + s_{i+1}).  right: centre ends on i+1, else on i.
-template <int RPL>
+template <int RPL, bool MIX>
 __device__ void two_site(const Slot& S, int i, bool right, bool is_swap, Shared& sh) {
-  move_centre_to<RPL>(S, i, sh);
+  move_centre_to<RPL, MIX>(S, i, sh);
+  using TS = TSite<MIX>;
   const z2* G = sh.G;
-  z2* A = site(S, i);
-  z2* B = site(S, i + 1);
+  TS* A = site<TS>(S, i);
+  TS* B = site<TS>(S, i + 1);
   const int cl = sh.bond[i], cm = sh.bond[i + 1], cr = sh.bond[i + 2];
   const int M = 2 * cl, N = 2 * cr;
   const int R = right ? M : N, C = right ? N : M;
   // theta[(a,s),(t,c)] = sum_b A[a,s,b] B[b,t,c] into W (row-major, M x N),
   // then theta'[(a,u),(v,c)] = sum_{s,t} G[uv][st] theta[(a,s),(t,c)] into Y0
   {
-    const gz2* aa = (const gz2*)A;
-    const gz2* bb = (const gz2*)B;
+    const glob<TS>* aa = (const glob<TS>*)A;
+    const glob<TS>* bb = (const glob<TS>*)B;
     gz2* ww = (gz2*)S.W;
-    zgemm(M, N, cm, [&](int i, int b) { return (z2)aa[(uint64_t)i * cm + b]; },
-          [&](int b, int j) { return (z2)bb[(uint64_t)b * N + j]; },
+    zgemm_p<MIX>(M, N, cm, [&](int i, int b) { return toz((TS)aa[(uint64_t)i * cm + b]); },
+          [&](int b, int j) { return toz((TS)bb[(uint64_t)b * N + j]); },
           [&](int i, int j, z2 v) { ww[(uint64_t)i * N + j] = v; });
   }
   __syncthreads();
@@ -1128,27 +1261,27 @@ __device__ void two_site(const Slot& S, int i, bool right, bool is_swap, Shared&
     }
   }
   __syncthreads();
-  const Factor f = factorise<RPL>(S.W, S.Y0, S.P, R, C, (int)S.chi, S.cutoff, true, sh, S.Jl);
+  const Factor f = factorise<RPL, MIX>(S.W, S.Y0, S.P, R, C, (int)S.chi, S.cutoff, true, sh, S.Jl, S.stop);
   const int k = f.k;
-  project(S.W, S.Y0, S.P, R, C, k, sh);
+  project<MIX>(S.W, S.Y0, S.P, R, C, k, sh);
   if (right) {
     // A_i[(a,u), j] = yhat_j ; A_{i+1}[j, (v,c)] = P[j, col] / ||sigma||
     for (int idx = threadIdx.x; idx < R * k; idx += NT) {
       const int row = idx / k, j = idx - row * k;
       const int pj = sh.perm[j];
-      A[idx] = cscale(S.W[(uint64_t)pj * R + row], 1.0 / sqrt(sh.sig2[pj]));
+      A[idx] = fromz<TS>(cscale(S.W[(uint64_t)pj * R + row], 1.0 / sqrt(sh.sig2[pj])));
     }
-    for (int idx = threadIdx.x; idx < k * C; idx += NT) B[idx] = cscale(S.P[idx], f.scale);
+    for (int idx = threadIdx.x; idx < k * C; idx += NT) B[idx] = fromz<TS>(cscale(S.P[idx], f.scale));
   } else {
     // A_{i+1}[j, (v,c)] = conj(yhat_j) ; A_i[(a,u), j] = conj(P[j, (a,u)]) / ||sigma||
     for (int idx = threadIdx.x; idx < k * R; idx += NT) {
       const int j = idx / R, col = idx - j * R;
       const int pj = sh.perm[j];
-      B[idx] = cconj(cscale(S.W[(uint64_t)pj * R + col], 1.0 / sqrt(sh.sig2[pj])));
+      B[idx] = fromz<TS>(cconj(cscale(S.W[(uint64_t)pj * R + col], 1.0 / sqrt(sh.sig2[pj]))));
     }
     for (int idx = threadIdx.x; idx < C * k; idx += NT) {
       const int row = idx / k, j = idx - row * k;
-      A[idx] = cconj(cscale(S.P[(uint64_t)j * C + row], f.scale));
+      A[idx] = fromz<TS>(cconj(cscale(S.P[(uint64_t)j * C + row], f.scale)));
     }
   }
   __syncthreads();
@@ -1164,7 +1297,7 @@ __device__ void two_site(const Slot& S, int i, bool right, bool is_swap, Shared&
   __syncthreads();
 }
 
-template <int RPL>
+template <int RPL, bool MIX>
 __device__ void swap_sites(const Slot& S, int i, bool right, Shared& sh) {
   if (threadIdx.x < 16) {
     const int r = threadIdx.x >> 2, c = threadIdx.x & 3;
@@ -1173,7 +1306,7 @@ __device__ void swap_sites(const Slot& S, int i, bool right, Shared& sh) {
     sh.G[threadIdx.x] = cmk(r == sw ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
-  two_site<RPL>(S, i, right, true, sh);
+  two_site<RPL, MIX>(S, i, right, true, sh);
   if (threadIdx.x == 0) {
     const int a = sh.qubit_at[i], b = sh.qubit_at[i + 1];
     sh.qubit_at[i] = (uint16_t)b;
@@ -1185,7 +1318,7 @@ __device__ void swap_sites(const Slot& S, int i, bool right, Shared& sh) {
 }
 
 // Apply the pending same-pair run (if any) and clear it.
-template <int RPL>
+template <int RPL, bool MIX>
 __device__ void flush(const Slot& S, Shared& sh) {
   if (!sh.p_active) return;
   const int qa = sh.p_qa, qb = sh.p_qb;
@@ -1196,8 +1329,8 @@ __device__ void flush(const Slot& S, Shared& sh) {
       Ua[e] = cmul(sh.pPhase, sh.pLa[e]);
       Ub[e] = sh.pLb[e];
     }
-    apply_local(S, sh.site_of[qa], Ua, sh);
-    apply_local(S, sh.site_of[qb], Ub, sh);
+    apply_local<MIX>(S, sh.site_of[qa], Ua, sh);
+    apply_local<MIX>(S, sh.site_of[qb], Ub, sh);
   } else {
     // Non-adjacent pair (the two ends of a ring kept as a chain): carry the
     // end qubit nearer the centre across, the last step being SWAP . G on
@@ -1208,10 +1341,10 @@ __device__ void flush(const Slot& S, Shared& sh) {
     const bool carry = hi - lo > 1;
     if (carry) {
       if (2 * sh.centre >= lo + hi) {
-        for (int s = hi - 1; s > lo; --s) swap_sites<RPL>(S, s, false, sh);
+        for (int s = hi - 1; s > lo; --s) swap_sites<RPL, MIX>(S, s, false, sh);
         at = lo;
       } else {
-        for (int s = lo; s < hi - 1; ++s) swap_sites<RPL>(S, s, true, sh);
+        for (int s = lo; s < hi - 1; ++s) swap_sites<RPL, MIX>(S, s, true, sh);
         at = hi - 1;
       }
       ia = sh.site_of[qa];
@@ -1227,7 +1360,7 @@ __device__ void flush(const Slot& S, Shared& sh) {
       sh.G[threadIdx.x] = sh.pM[rr * 4 + cc];
     }
     __syncthreads();
-    two_site<RPL>(S, at, true, false, sh);
+    two_site<RPL, MIX>(S, at, true, false, sh);
     if (carry && threadIdx.x == 0) {
       const int a = sh.qubit_at[at], b = sh.qubit_at[at + 1];
       sh.qubit_at[at] = (uint16_t)b;
@@ -1242,13 +1375,13 @@ __device__ void flush(const Slot& S, Shared& sh) {
 }
 
 // Process one sampled non-identity gate (setting 1 = B, 2 = C) of row r.
-template <int RPL>
+template <int RPL, bool MIX>
 __device__ void process_gate(const Slot& S, const DevRow& row, int setting, int layer_unused,
                              Shared& sh) {
   (void)layer_unused;
   if (row.nq == 1) {
     const int q = row.q0;
-    if (sh.p_active && (q == sh.p_qa || q == sh.p_qb)) flush<RPL>(S, sh);
+    if (sh.p_active && (q == sh.p_qa || q == sh.p_qb)) flush<RPL, MIX>(S, sh);
     z2 U[4];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
@@ -1260,12 +1393,12 @@ __device__ void process_gate(const Slot& S, const DevRow& row, int setting, int 
         U[r * 2 + c] = cmk((r == c ? cb : 0.0) + sb * P.y, -sb * P.x);
       }
     }
-    apply_local(S, sh.site_of[q], U, sh);
+    apply_local<MIX>(S, sh.site_of[q], U, sh);
     return;
   }
   const int qa = row.q0, qb = row.q1;
   if (sh.p_active && !((qa == sh.p_qa && qb == sh.p_qb) || (qa == sh.p_qb && qb == sh.p_qa)))
-    flush<RPL>(S, sh);
+    flush<RPL, MIX>(S, sh);
   if (threadIdx.x == 0) {
     if (!sh.p_active) {
       sh.p_active = 1;
@@ -1377,30 +1510,34 @@ __device__ void store_state(const EngineArgs& a, int slot, Shared& sh, uint32_t 
   }
 }
 
+template <bool MIX>
 __device__ Slot make_slot(const EngineArgs& a, int slot, z2* Jl) {
   Slot S;
   S.Jl = Jl;
   S.ss = a.site_stride;
-  S.T = reinterpret_cast<z2*>(a.tensors) + (uint64_t)slot * a.n * a.site_stride;
+  S.T = reinterpret_cast<TSite<MIX>*>(a.tensors) + (uint64_t)slot * a.n * a.site_stride;
   const uint64_t q = a.work_stride / 3;
   S.Y0 = reinterpret_cast<z2*>(a.work) + (uint64_t)slot * a.work_stride;
   S.W = S.Y0 + q;
   S.P = S.W + q;
   S.cutoff = a.cutoff;
+  S.stop = a.stop_tan;
   S.chi = a.states[slot].chi_cap;
   S.n = a.n;
   return S;
 }
 
 // ---------------------------------------------------------------- kernels
+template <bool MIX>
 __global__ __launch_bounds__(NT) void init_kernel(EngineArgs a) {
+  using TS = TSite<MIX>;
   const int slot = blockIdx.x;
   SampleState* st = a.states + slot;
-  z2* T = reinterpret_cast<z2*>(a.tensors) + (uint64_t)slot * a.n * a.site_stride;
+  TS* T = reinterpret_cast<TS*>(a.tensors) + (uint64_t)slot * a.n * a.site_stride;
   for (int k = threadIdx.x; k < (int)a.n; k += NT) {
     const int bit = a.init_bits[k] ? 1 : 0;
-    T[(uint64_t)k * a.site_stride + 0] = cmk(bit ? 0.0 : 1.0, 0.0);
-    T[(uint64_t)k * a.site_stride + 1] = cmk(bit ? 1.0 : 0.0, 0.0);
+    T[(uint64_t)k * a.site_stride + 0] = fromz<TS>(cmk(bit ? 0.0 : 1.0, 0.0));
+    T[(uint64_t)k * a.site_stride + 1] = fromz<TS>(cmk(bit ? 1.0 : 0.0, 0.0));
   }
   for (int k = threadIdx.x; k <= (int)a.n; k += NT) st->bond[k] = 1;
   for (int k = threadIdx.x; k < (int)a.n; k += NT) st->qubit_at[k] = (uint16_t)k;
@@ -1418,12 +1555,12 @@ __global__ __launch_bounds__(NT) void init_kernel(EngineArgs a) {
   }
 }
 
-template <int RPL>
+template <int RPL, bool MIX>
 __global__ __launch_bounds__(NT) void evolve_kernel(EngineArgs a, uint32_t n_layers) {
   __shared__ Shared sh;
   __shared__ z2 Jl[jl_size<RPL>()];
   const int slot = blockIdx.x;
-  const Slot S = make_slot(a, slot, Jl);
+  const Slot S = make_slot<MIX>(a, slot, Jl);
   load_state(a, slot, sh);
   const uint32_t sample = (uint32_t)(a.first_sample + slot);
   const uint32_t L = a.l_eff;
@@ -1447,9 +1584,9 @@ __global__ __launch_bounds__(NT) void evolve_kernel(EngineArgs a, uint32_t n_lay
     for (uint32_t r = 0; r < L; ++r) {
       const int c = sh.choice[r];
       if (c == 0) continue;
-      process_gate<RPL>(S, a.rows[r], c, (int)layer, sh);
+      process_gate<RPL, MIX>(S, a.rows[r], c, (int)layer, sh);
     }
-    flush<RPL>(S, sh);     // runs end at Trotter-step boundaries
+    flush<RPL, MIX>(S, sh);     // runs end at Trotter-step boundaries
     __syncthreads();  // every thread is done reading this step's settings
   }
   store_state(a, slot, sh, layer0 + n_layers);
@@ -1459,26 +1596,29 @@ __global__ __launch_bounds__(NT) void evolve_kernel(EngineArgs a, uint32_t n_lay
 // evaluate every Pauli string whose first site is c by a transfer-matrix
 // contraction from c (left part left-canonical) to its last site (right part
 // right-canonical), normalised by the centre's squared norm.
-template <int RPL>
+template <int RPL, bool MIX>
 __global__ __launch_bounds__(NT) void observe_kernel(EngineArgs a, double* values,
                                                      double* weights) {
   __shared__ Shared sh;
   __shared__ z2 Jl[jl_size<RPL>()];
   __shared__ double acc_obs[256];
   const int slot = blockIdx.x;
-  const Slot S = make_slot(a, slot, Jl);
+  const Slot S = make_slot<MIX>(a, slot, Jl);
   load_state(a, slot, sh);
   const double obs_cut = 1e-30;    // gauge-only shifts
   for (int o = threadIdx.x; o < 256; o += NT) acc_obs[o] = 0.0;
-  while (sh.centre > 0) shift_left<RPL>(S, sh.centre, obs_cut, sh);
+  while (sh.centre > 0) shift_left<RPL, MIX>(S, sh.centre, obs_cut, sh);
   z2* E = S.Y0;
   z2* F = S.W;
   for (int c = 0; c < (int)a.n; ++c) {
-    const z2* Ac = site(S, c);
+    using TS = TSite<MIX>;
+    const TS* Ac = site<TS>(S, c);
     const int cl = sh.bond[c], cr = sh.bond[c + 1];
     double nn = 0.0;
-    for (int idx = threadIdx.x; idx < cl * 2 * cr; idx += NT)
-      nn += Ac[idx].x * Ac[idx].x + Ac[idx].y * Ac[idx].y;
+    for (int idx = threadIdx.x; idx < cl * 2 * cr; idx += NT) {
+      const z2 v = toz(Ac[idx]);
+      nn += v.x * v.x + v.y * v.y;
+    }
     const double norm2 = block_sum(nn, sh.red);
     for (uint32_t si = 0; si < a.n_strings; ++si) {
       const DevString str = a.strings[si];
@@ -1495,7 +1635,7 @@ __global__ __launch_bounds__(NT) void observe_kernel(EngineArgs a, double* value
         E[idx] = cmk((idx / dl) == (idx % dl) ? 1.0 : 0.0, 0.0);
       __syncthreads();
       for (int k = c; k <= last; ++k) {
-        const z2* A = site(S, k);
+        const TS* A = site<TS>(S, k);
         const int kl = sh.bond[k], kr = sh.bond[k + 1];
         // operator on this site (product of the string's factors here)
         z2 O[4] = {cmk(1, 0), cmk(0, 0), cmk(0, 0), cmk(1, 0)};
@@ -1514,7 +1654,7 @@ __global__ __launch_bounds__(NT) void observe_kernel(EngineArgs a, double* value
         for (int idx = threadIdx.x; idx < kl * 2 * kr; idx += NT) {
           const int ap = idx / (2 * kr), sb = idx - ap * 2 * kr;
           z2 v = cmk(0, 0);
-          for (int aa = 0; aa < kl; ++aa) cfma(v, E[ap * kl + aa], A[(uint64_t)aa * 2 * kr + sb]);
+          for (int aa = 0; aa < kl; ++aa) cfma(v, E[ap * kl + aa], toz(A[(uint64_t)aa * 2 * kr + sb]));
           F[idx] = v;
         }
         __syncthreads();
@@ -1530,8 +1670,8 @@ __global__ __launch_bounds__(NT) void observe_kernel(EngineArgs a, double* value
             cfma(of0, O[1], f1);
             cfma(of1, O[2], f0);
             cfma(of1, O[3], f1);
-            cfmac(v, A[(uint64_t)ap * 2 * kr + 0 * kr + bp], of0);
-            cfmac(v, A[(uint64_t)ap * 2 * kr + 1 * kr + bp], of1);
+            cfmac(v, toz(A[(uint64_t)ap * 2 * kr + 0 * kr + bp]), of0);
+            cfmac(v, toz(A[(uint64_t)ap * 2 * kr + 1 * kr + bp]), of1);
           }
           F[kl * 2 * kr + idx] = v;     // stage after F's live part
         }
@@ -1546,7 +1686,7 @@ __global__ __launch_bounds__(NT) void observe_kernel(EngineArgs a, double* value
       if (threadIdx.x == 0) acc_obs[str.observable] += str.coeff * tr / norm2;
       __syncthreads();
     }
-    if (c + 1 < (int)a.n) shift_right<RPL>(S, c, obs_cut, sh);
+    if (c + 1 < (int)a.n) shift_right<RPL, MIX>(S, c, obs_cut, sh);
   }
   __syncthreads();
   const SampleState* st = a.states + slot;
@@ -1633,7 +1773,10 @@ __global__ __launch_bounds__(NT) void sample_write_kernel(const DevRow* rows, ui
 }  // namespace
 
 hipError_t launch_init(const EngineArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(init_kernel, dim3(a.count), dim3(NT), 0, s, a);
+  if (a.mixed)
+    hipLaunchKernelGGL(init_kernel<true>, dim3(a.count), dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL(init_kernel<false>, dim3(a.count), dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1643,24 +1786,40 @@ static int rows_per_lane(uint32_t chi_max) {
   return r <= 64 ? 1 : r <= 128 ? 2 : r <= 256 ? 4 : 8;
 }
 
-hipError_t launch_evolve(const EngineArgs& a, uint32_t n_layers, hipStream_t s) {
+template <bool MIX>
+static void evolve_rpl(const EngineArgs& a, uint32_t n_layers, hipStream_t s) {
   switch (rows_per_lane(a.chi_max)) {
-    case 1: hipLaunchKernelGGL(evolve_kernel<1>, dim3(a.count), dim3(NT), 0, s, a, n_layers); break;
-    case 2: hipLaunchKernelGGL(evolve_kernel<2>, dim3(a.count), dim3(NT), 0, s, a, n_layers); break;
-    case 4: hipLaunchKernelGGL(evolve_kernel<4>, dim3(a.count), dim3(NT), 0, s, a, n_layers); break;
-    default: hipLaunchKernelGGL(evolve_kernel<8>, dim3(a.count), dim3(NT), 0, s, a, n_layers); break;
+    case 1: hipLaunchKernelGGL((evolve_kernel<1, MIX>), dim3(a.count), dim3(NT), 0, s, a, n_layers); break;
+    case 2: hipLaunchKernelGGL((evolve_kernel<2, MIX>), dim3(a.count), dim3(NT), 0, s, a, n_layers); break;
+    case 4: hipLaunchKernelGGL((evolve_kernel<4, MIX>), dim3(a.count), dim3(NT), 0, s, a, n_layers); break;
+    default: hipLaunchKernelGGL((evolve_kernel<8, MIX>), dim3(a.count), dim3(NT), 0, s, a, n_layers); break;
   }
+}
+
+hipError_t launch_evolve(const EngineArgs& a, uint32_t n_layers, hipStream_t s) {
+  if (a.mixed)
+    evolve_rpl<true>(a, n_layers, s);
+  else
+    evolve_rpl<false>(a, n_layers, s);
   return hipGetLastError();
+}
+
+template <bool MIX>
+static void observe_rpl(const EngineArgs& a, double* v, double* w, hipStream_t s) {
+  switch (rows_per_lane(a.chi_max)) {
+    case 1: hipLaunchKernelGGL((observe_kernel<1, MIX>), dim3(a.count), dim3(NT), 0, s, a, v, w); break;
+    case 2: hipLaunchKernelGGL((observe_kernel<2, MIX>), dim3(a.count), dim3(NT), 0, s, a, v, w); break;
+    case 4: hipLaunchKernelGGL((observe_kernel<4, MIX>), dim3(a.count), dim3(NT), 0, s, a, v, w); break;
+    default: hipLaunchKernelGGL((observe_kernel<8, MIX>), dim3(a.count), dim3(NT), 0, s, a, v, w); break;
+  }
 }
 
 hipError_t launch_observe(const EngineArgs& a, double* d_values, double* d_weights,
                           hipStream_t s) {
-  switch (rows_per_lane(a.chi_max)) {
-    case 1: hipLaunchKernelGGL(observe_kernel<1>, dim3(a.count), dim3(NT), 0, s, a, d_values, d_weights); break;
-    case 2: hipLaunchKernelGGL(observe_kernel<2>, dim3(a.count), dim3(NT), 0, s, a, d_values, d_weights); break;
-    case 4: hipLaunchKernelGGL(observe_kernel<4>, dim3(a.count), dim3(NT), 0, s, a, d_values, d_weights); break;
-    default: hipLaunchKernelGGL(observe_kernel<8>, dim3(a.count), dim3(NT), 0, s, a, d_values, d_weights); break;
-  }
+  if (a.mixed)
+    observe_rpl<true>(a, d_values, d_weights, s);
+  else
+    observe_rpl<false>(a, d_values, d_weights, s);
   return hipGetLastError();
 }
 

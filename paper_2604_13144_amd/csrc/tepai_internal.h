@@ -15,7 +15,10 @@ constexpr int kMaxChi = 256;
 constexpr int kMaxRows = 4096;        // PAI table rows per Trotter step
 constexpr int kMaxStringOps = 8;
 constexpr int kThreads = 512;         // engine block: eight wave64 wavefronts
-constexpr int kMaxSweeps = 60;        // Jacobi sweep cap per factorisation
+constexpr int kMaxSweeps = 60;
+constexpr double kStopTanFp64 = 1e-8;    // FP64 path: residual ~1e-16
+constexpr double kStopTanMixed = 1e-5;   // mixed path: residual ~1e-10
+constexpr double kCutoffMixed = 1e-7;    // mixed path: relative singular-value floor        // Jacobi sweep cap per factorisation
 
 // One row of the PAI table: a (sub-)rotation of one Trotter step.
 struct DevRow {
@@ -58,10 +61,11 @@ struct EngineArgs {
   double2* tensors;       // [count][n][site_stride]
   double2* work;          // [count][work_stride]
   uint64_t site_stride;   // complex elements per site slot: 2 chi_max^2
-  uint64_t work_stride;   // complex elements of scratch per sample
+  uint64_t work_stride;   // complex elements of scratch per sample: 3 max((2 chi_max)^2, kThreads)
   uint64_t first_sample;  // global index of slot 0
   uint64_t seed;
   double cutoff;
+  double stop_tan;        // Jacobi stop: a sweep whose rotations all have |tan| <= this
   double log_g1_step;
   uint32_t l_eff;
   uint32_t n;
@@ -69,6 +73,7 @@ struct EngineArgs {
   uint32_t count;
   uint32_t n_strings;
   uint32_t n_obs;
+  uint32_t mixed;         // 1: TEPAI_FP32_MIXED (complex64 site tensors)
 };
 
 // Kernel launchers (kernels.hip).

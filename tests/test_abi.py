@@ -121,6 +121,24 @@ def test_valid_configs_pass_and_wrap_bond_is_adjacent():
     L.tepai_validate(None, L.ProblemStruct(bad(terms=(ti.Term("XX", (7, 0), 1.0),))))
 
 
+def test_precision_codes():
+    ps = L.ProblemStruct(ti.config(1), precision=L.TEPAI_FP32_MIXED)
+    L.tepai_validate(None, ps)
+    with pytest.raises(L.TepaiError) as e:
+        L.tepai_validate(None, L.ProblemStruct(ti.config(1), precision=2))
+    assert e.value.status == -1
+
+
+def test_mixed_workspace_stores_complex64_site_tensors():
+    p = ti.config(4)
+    d64 = (L.tepai_workspace_size(None, L.ProblemStruct(p), 8)
+           - L.tepai_workspace_size(None, L.ProblemStruct(p), 1)) / 7
+    d32 = (L.tepai_workspace_size(None, L.ProblemStruct(p, precision=L.TEPAI_FP32_MIXED), 8)
+           - L.tepai_workspace_size(None, L.ProblemStruct(p, precision=L.TEPAI_FP32_MIXED), 1)) / 7
+    chi, n = 128, 64
+    assert abs((d64 - d32) - 8 * n * 2 * chi * chi) / (8 * n * 2 * chi * chi) < 0.01
+
+
 def test_workspace_size_scales_with_batch():
     ps = L.ProblemStruct(ti.config(4))
     s1 = L.tepai_workspace_size(None, ps, 1)

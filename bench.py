@@ -42,6 +42,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector (and FP64 MFMA), dense
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "evolve_kernel_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2604_13144_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic():
+    """HBM-side bytes per launch of the mixed evolve kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs (calibrated by a 1 GiB copy), or
+    None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_RECORD))
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    return rec["traffic_bytes_per_launch"] if rec.get("kernels_hip_sha256") == sha else None
 
 
 def parse():
@@ -53,7 +68,24 @@ def parse():
     ap.add_argument("--layers-per-step", type=int, default=8)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--paths", default="mixed,fp64",
+                    help="comma list of paths to time (the first one gives value)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device (counter calibration) and exit")
     return ap.parse_args()
+
+
+def copy_probe(mib: int):
+    """One plain device copy of known size: its FETCH_SIZE / WRITE_SIZE counter
+    readings calibrate those counters against bytes actually moved."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8}))
 
 
 def workload(batch):
@@ -170,6 +202,9 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if a.copy_probe:
+        copy_probe(a.copy_probe)
+        return
     import numpy as np
     import torch
     torch.cuda.init()          # torch's HIP context first, then the library's handle
@@ -180,8 +215,17 @@ def main():
     if (W + K) * J > p.trotter_steps:
         raise SystemExit("warmup + steps exceed the circuit")
     h = L.Handle(0)
-    mixed = run_path(L, h, p, L.TEPAI_FP32_MIXED, J, K, W, B)
-    plain = run_path(L, h, p, L.TEPAI_FP64, J, K, W, B)
+    paths = a.paths.split(",")
+    mixed = run_path(L, h, p, L.TEPAI_FP32_MIXED, J, K, W, B) if "mixed" in paths else None
+    plain = run_path(L, h, p, L.TEPAI_FP64, J, K, W, B) if "fp64" in paths else None
+    if mixed is None or plain is None:
+        # one path only (profiling runs): report it alone
+        r = mixed or plain
+        print(json.dumps({"path": "mixed" if mixed else "fp64", "value": r["value"], "unit": "samples/s",
+                          "kernel_ms_per_launch": r["kernel_ms_per_launch"],
+                          "flops_per_launch": r["flops_per_launch"],
+                          "timed_trotter_steps": [W * J, (W + K) * J]}))
+        return
     err = float(np.max(np.abs(mixed["values"] - plain["values"])))
     est_err = float(np.max(np.abs(mixed["mean"] - plain["mean"])))
     line = {
@@ -216,7 +260,8 @@ def main():
         "max_sample_err_mixed_vs_fp64": err,
         "max_estimator_err_mixed_vs_fp64": est_err,
         "roofline": {"bound": "alu", "achieved": mixed["achieved"], "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": mixed["achieved"] / FP64_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": mixed["achieved"] / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic(),
                      "kernel": "evolve_kernel (mixed)",
                      "kernel_ms_per_launch": mixed["kernel_ms_per_launch"],
                      "flops_per_launch": mixed["flops_per_launch"],

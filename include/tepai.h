@@ -63,6 +63,14 @@ enum { TEPAI_PAULI_I = 0, TEPAI_PAULI_X = 1, TEPAI_PAULI_Y = 2, TEPAI_PAULI_Z = 
 /* Gate setting codes of a sampled rotation (appendix "PAI & TE-PAI", eq. settings). */
 enum { TEPAI_SET_A = 0, TEPAI_SET_B = 1, TEPAI_SET_C = 2 };
 
+/* tepai_problem.flags.
+ * TEPAI_NO_PI: the biased variant without pi rotations (appendix "Proof of
+ *   Statement 3"): each rotation is A with probability 1 - lambda and B with
+ *   probability lambda = |theta| / Delta; every sign is +1, ||g||_1 = 1 and
+ *   all weights are 1, at a per-gate bias |theta| (Delta - |theta|) / 2
+ *   R''(0) + O(Delta^3). */
+enum { TEPAI_NO_PI = 1u };
+
 /* Storage / arithmetic precision of the MPS path.
  * TEPAI_FP64: complex128 site tensors and FP64 throughout; per-sample values
  *   agree with an exact-arithmetic evaluation of the same truncated
@@ -115,7 +123,7 @@ typedef struct {
   uint32_t n_strings;
   const tepai_pauli_string* strings;
   uint32_t precision;           /* TEPAI_FP64 or TEPAI_FP32_MIXED */
-  uint32_t flags;               /* reserved, 0 */
+  uint32_t flags;               /* 0 or TEPAI_NO_PI */
 } tepai_problem;
 
 /* Per-sample counters (cost model of eq. Wsample and truncation record). */

@@ -14,6 +14,12 @@ Reading taken where the paper assumes |theta| <= Delta: a rotation with
 identical rotations R_k(theta_k / m_k) (same generator, so their product is
 exactly R_k(theta_k) and the Trotter circuit is unchanged).
 
+Biased variant without pi rotations (appendix "Proof of Statement 3"): the
+gate is approximated by A and B only, with gamma~ = (1 - lambda, lambda, 0),
+lambda = |theta| / Delta; both are non-negative, ||gamma~||_1 = 1 exactly,
+every sign is +1 and ||g||_1 = 1, at the price of a per-gate bias
+|theta| (Delta - |theta|) / 2 R''(0) + O(Delta^3).
+
 Each table row holds one (sub-)rotation of one Trotter step.  The sampler
 takes the top 63 bits v = u >> 1 of a 64-bit uniform u and compares them with
 two integer thresholds:
@@ -39,6 +45,12 @@ def gammas(theta_abs: float, delta: float) -> Tuple[float, float, float]:
     g2 = math.sin(t) / math.sin(delta)
     g3 = -math.sin(t / 2.0) * math.sin(delta / 2.0 - t / 2.0) / math.cos(delta / 2.0)
     return g1, g2, g3
+
+
+def gammas_no_pi(theta_abs: float, delta: float) -> Tuple[float, float, float]:
+    """(1 - lambda, lambda, 0) with lambda = |theta| / Delta (no-pi variant)."""
+    lam = theta_abs / delta
+    return 1.0 - lam, lam, 0.0
 
 
 def to_threshold(p: float) -> int:
@@ -95,11 +107,17 @@ def build_table(problem) -> Table:
             m = int(math.ceil(abs(theta) / delta))
             n_split += 1
         sub = theta / m
-        g = gammas(abs(sub), delta)
-        nrm = abs(g[0]) + abs(g[1]) + abs(g[2])
-        p = (abs(g[0]) / nrm, abs(g[1]) / nrm, abs(g[2]) / nrm)
-        row = Row(term=k, theta=sub, gamma=g, norm1=nrm, p=p,
-                  t1=to_threshold(p[0]), t2=to_threshold(p[0] + p[1]))
+        if getattr(problem, "no_pi", False):
+            # probabilities are the coefficients themselves; C is never drawn
+            g = gammas_no_pi(abs(sub), delta)
+            row = Row(term=k, theta=sub, gamma=g, norm1=1.0, p=g,
+                      t1=to_threshold(g[0]), t2=T_ONE)
+        else:
+            g = gammas(abs(sub), delta)
+            nrm = abs(g[0]) + abs(g[1]) + abs(g[2])
+            p = (abs(g[0]) / nrm, abs(g[1]) / nrm, abs(g[2]) / nrm)
+            row = Row(term=k, theta=sub, gamma=g, norm1=nrm, p=p,
+                      t1=to_threshold(p[0]), t2=to_threshold(p[0] + p[1]))
         rows.extend([row] * m)
     log_step = 0.0
     for r in rows:

@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "TEPAI_OK", -1: "TEPAI_EINVAL", -2: "TEPAI_ERANGE", -3: "TEPA
 PAULI_CODE = {"X": 1, "Y": 2, "Z": 3}
 TEPAI_FP64 = 0
 TEPAI_FP32_MIXED = 1
+TEPAI_NO_PI = 1
 
 
 class tepai_term(C.Structure):
@@ -177,7 +178,7 @@ class ProblemStruct:
         s.n_strings = len(strings)
         s.strings = C.cast(self._strings, C.POINTER(tepai_pauli_string))
         s.precision = int(precision)
-        s.flags = 0
+        s.flags = TEPAI_NO_PI if getattr(p, "no_pi", False) else 0
         self.struct = s
         self.n_obs = s.n_obs
 

@@ -78,11 +78,22 @@ Table build_table(const tepai_problem& p) {
     HostRow r;
     r.term = k;
     r.theta = theta / (double)m;
-    pai_gammas(std::fabs(r.theta), p.delta, r.g);
-    r.norm1 = std::fabs(r.g[0]) + std::fabs(r.g[1]) + std::fabs(r.g[2]);
-    const double p1 = std::fabs(r.g[0]) / r.norm1, p2 = std::fabs(r.g[1]) / r.norm1;
-    r.t1 = threshold(p1);
-    r.t2 = threshold(p1 + p2);
+    if (p.flags & TEPAI_NO_PI) {
+      // gamma~ = (1 - lambda, lambda, 0): probabilities themselves, ||.||_1 = 1
+      const double lam = std::fabs(r.theta) / p.delta;
+      r.g[0] = 1.0 - lam;
+      r.g[1] = lam;
+      r.g[2] = 0.0;
+      r.norm1 = 1.0;
+      r.t1 = threshold(r.g[0]);
+      r.t2 = kThresholdOne;
+    } else {
+      pai_gammas(std::fabs(r.theta), p.delta, r.g);
+      r.norm1 = std::fabs(r.g[0]) + std::fabs(r.g[1]) + std::fabs(r.g[2]);
+      const double p1 = std::fabs(r.g[0]) / r.norm1, p2 = std::fabs(r.g[1]) / r.norm1;
+      r.t1 = threshold(p1);
+      r.t2 = threshold(p1 + p2);
+    }
     for (uint32_t i = 0; i < m; ++i) t.rows.push_back(r);
   }
   for (const HostRow& r : t.rows) t.log_step += std::log(r.norm1);
@@ -163,7 +174,7 @@ tepai_status validate(tepai_handle* h, const tepai_problem* p) {
   }
   if (p->precision != TEPAI_FP64 && p->precision != TEPAI_FP32_MIXED)
     return fail(h, TEPAI_EINVAL, "unsupported precision");
-  if (p->flags != 0) return fail(h, TEPAI_EINVAL, "unsupported flags");
+  if ((p->flags & ~(uint32_t)TEPAI_NO_PI) != 0) return fail(h, TEPAI_EINVAL, "unsupported flags");
   return TEPAI_OK;
 }
 

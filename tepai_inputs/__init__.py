@@ -70,6 +70,7 @@ class Problem:
     sample_offset: int = 0
     svd_cutoff: float = 1e-12
     chi_per_sample: Optional[Tuple[int, ...]] = None
+    no_pi: bool = False         # biased variant without pi rotations
     name: str = ""
 
     def with_(self, **kw) -> "Problem":

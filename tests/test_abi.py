@@ -70,9 +70,10 @@ int main(void) {
             assert C.sizeof(ct[k]) == int(v), k
 
 
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
-def test_host_table_equals_oracle_table(k):
-    p = ti.config(k)
+@pytest.mark.parametrize("k,no_pi", [(1, False), (2, False), (3, False), (4, False), (5, False),
+                                      (1, True), (4, True)])
+def test_host_table_equals_oracle_table(k, no_pi):
+    p = ti.config(k).with_(no_pi=no_pi)
     t = L.tepai_pai_table(None, L.ProblemStruct(p))
     o = pai.build_table(p)
     assert t["l_eff"] == o.l_eff
@@ -83,6 +84,8 @@ def test_host_table_equals_oracle_table(k):
     thr = np.array([[r.t1, r.t2] for r in o.rows], dtype=np.uint64)
     assert np.array_equal(t["thresholds"], thr)          # bit-exact sampler decisions
     assert abs(t["log_g1_step"] - o.log_g1_step) <= 1e-14 * abs(o.log_g1_step)
+    if no_pi:
+        assert t["log_g1_step"] == 0.0 and np.all(t["thresholds"][:, 1] == 2 ** 63)
 
 
 def bad(**kw):

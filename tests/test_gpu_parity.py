@@ -148,6 +148,16 @@ def test_edge_cases(handle):
     assert np.all(np.isnan(out["std_err"]))
 
 
+def test_no_pi_variant(handle):
+    # biased variant without pi rotations: weights exactly 1, same MPS path
+    p = ti.small_ring(10, seed=4, T=0.5, N=12, delta=math.pi / 16, chi=8, n_samples=6)
+    p = p.with_(no_pi=True)
+    print("parity: no-pi ring n=10 chi=8", flush=True)
+    vals, wts, st = gpu_batch(handle, p, 0, 6, [5, 7])
+    assert np.all(wts == 1.0) and np.all(st["sign"] == 1)
+    compare(p, range(6), vals, wts, st, 0)
+
+
 def test_heterogeneous_chi_per_sample(handle):
     p = ti.small_ring(10, seed=7, T=0.4, N=10, delta=math.pi / 16, chi=8, n_samples=6)
     p = p.with_(chi_per_sample=(2, 4, 8, 3, 8, 5))
@@ -158,3 +168,32 @@ def test_heterogeneous_chi_per_sample(handle):
         r = run_sample(p, t, i)
         if not r.stats.ties:
             assert np.max(np.abs(vals[i] - r.values)) <= value_tol(r)
+
+
+def test_time_series_checkpoints(handle):
+    # one batch read out after 4, 8 and 12 Trotter steps: each read-out is the
+    # TE-PAI estimate at time jT/N (prefix samples, weight sign_j ||g||_1(j))
+    p = ti.small_ring(10, seed=8, T=0.6, N=12, delta=math.pi / 16, chi=8, n_samples=5)
+    ps = L.ProblemStruct(p)
+    dev = torch.device("cuda", 0)
+    b = L.Batch(handle, ps, 0, 5)
+    v = torch.empty(5 * ps.n_obs, dtype=torch.float64, device=dev)
+    w = torch.empty(5, dtype=torch.float64, device=dev)
+    mean = torch.empty(ps.n_obs, dtype=torch.float64, device=dev)
+    se = torch.empty(ps.n_obs, dtype=torch.float64, device=dev)
+    t = pai.build_table(p)
+    for j in (4, 8, 12):
+        b.evolve(4)
+        b.observe(v, w)
+        L.tepai_reduce(handle, 5, ps.n_obs, v, w, mean, se)
+        torch.cuda.synchronize()
+        vals = v.cpu().numpy().reshape(5, ps.n_obs)
+        res = [run_sample(p, t, s, j) for s in range(5)]
+        for s, r in enumerate(res):
+            assert float(w[s]) * r.sign > 0
+            assert abs(abs(float(w[s])) - math.exp(t.log_g1(j))) <= 1e-14 * math.exp(t.log_g1(j))
+            if not r.stats.ties:
+                assert np.max(np.abs(vals[s] - r.values)) <= value_tol(r)
+        ws = np.array([r.sign * math.exp(t.log_g1(j)) for r in res])
+        m, _, _ = estimate(np.array([r.values for r in res]), ws)
+        assert np.max(np.abs(mean.cpu().numpy() - m)) <= 1e-9

@@ -43,6 +43,13 @@ def test_sampler_cfg4_subset_and_prefix(handle):
     check_bit_exact(handle, p, list(range(5, 9)), layers=37)
 
 
+def test_sampler_no_pi_variant(handle):
+    p = ti.config(4).with_(no_pi=True)
+    check_bit_exact(handle, p, list(range(0, 8)))
+    _, words, signs = L.tepai_sample_circuits(handle, L.ProblemStruct(p), 0, 8, 0)
+    assert np.all(signs == 1) and not np.any((words.astype(np.uint64) & np.uint64(3)) == 2)
+
+
 def test_sampler_offset_and_seed(handle):
     p = ti.config(2).with_(sample_offset=123_456, seed=0xDEADBEEFCAFEF00D, n_samples=64)
     check_bit_exact(handle, p, list(range(0, 16)))

@@ -104,6 +104,25 @@ typedef struct {
   double coeff;
 } tepai_pauli_string;
 
+/* A starting state shared by every sample (hybrid start: e.g. the state a
+ * deep Trotter circuit reached at t0, from which the TE-PAI segment of
+ * duration total_time continues; sec. "Implementation", Trotter-then-TE-PAI).
+ * Site k of the chain holds A_k[a][s][c] of shape bond[k] x 2 x bond[k+1],
+ * row-major, as interleaved (re, im) doubles; the sites are concatenated in
+ * order.  qubit_at[k] is the qubit held at site k (NULL: qubit k).  Sites
+ * left of `centre` must be left-canonical and sites right of it
+ * right-canonical (not checked: truncations are optimal only in that form).
+ * bond[0] = bond[n] = 1, and no bond may exceed the smallest bond cap of the
+ * samples.  Caller-owned; the library copies it in tepai_batch_create (and
+ * tepai_run) and keeps no pointer. */
+typedef struct {
+  const uint32_t* bond;         /* [n_qubits + 1] */
+  const double* tensors;        /* sum_k 2 bond[k] bond[k+1] complex values */
+  const uint32_t* qubit_at;     /* [n_qubits] or NULL */
+  uint32_t centre;              /* orthogonality centre site, < n_qubits */
+  uint32_t reserved;            /* 0 */
+} tepai_mps;
+
 typedef struct {
   uint32_t n_qubits;            /* 2 .. 256 */
   uint32_t n_terms;
@@ -118,12 +137,14 @@ typedef struct {
   const uint32_t* chi_per_sample; /* nullable; [n_samples] caps <= chi_max */
   double svd_cutoff;            /* relative singular-value floor, >= 0 (the mixed
                                    path uses max(svd_cutoff, 1e-7)) */
-  const uint8_t* initial_bits;  /* [n_qubits] computational-basis start, 0/1 */
+  const uint8_t* initial_bits;  /* [n_qubits] computational-basis start, 0/1
+                                   (ignored when initial_mps is given) */
   uint32_t n_obs;
   uint32_t n_strings;
   const tepai_pauli_string* strings;
   uint32_t precision;           /* TEPAI_FP64 or TEPAI_FP32_MIXED */
   uint32_t flags;               /* 0 or TEPAI_NO_PI */
+  const tepai_mps* initial_mps; /* NULL: start from initial_bits */
 } tepai_problem;
 
 /* Per-sample counters (cost model of eq. Wsample and truncation record). */

@@ -59,6 +59,14 @@ class MPS:
         self.cutoff = cutoff
         self.stats = Stats()
 
+    @classmethod
+    def from_initial(cls, init, cutoff: float = 1e-12) -> "MPS":
+        """A copy of a given mixed-canonical MPS (site order as given)."""
+        m = cls("0" * len(init.tensors), cutoff)
+        m.A = [np.array(a, dtype=complex, copy=True) for a in init.tensors]
+        m.centre = init.centre
+        return m
+
     # -- single-site ------------------------------------------------------
     def apply_local(self, site: int, U: np.ndarray):
         self.A[site] = np.einsum("st,atb->asb", U, self.A[site])

@@ -60,7 +60,9 @@ def observable_value(mps: MPS, qubit_at, observable) -> float:
 def run_sample(problem, table, s: int, layers: Optional[int] = None) -> SampleResult:
     circ = sample_circuit(problem, table, s, layers)
     ops, qubit_at = build_schedule(problem, table, circ, chi_of(problem, s))
-    mps = MPS(problem.initial_bits, problem.svd_cutoff).run(ops)
+    init = getattr(problem, "initial_mps", None)
+    mps = (MPS.from_initial(init, problem.svd_cutoff) if init is not None
+           else MPS(problem.initial_bits, problem.svd_cutoff)).run(ops)
     vals = np.array([observable_value(mps, qubit_at, o) for o in problem.observables])
     return SampleResult(sample=s, sign=circ.sign, n_gates=circ.n_gates, values=vals,
                         stats=mps.stats, bonds=mps.bonds())

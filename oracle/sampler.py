@@ -20,6 +20,7 @@ from .philox import uniform_u64
 
 SET_B = 1
 SET_C = 2
+SET_EXACT = 3     # not drawn: the exact rotation R(theta), for deterministic Trotter circuits
 
 
 @dataclass(frozen=True)

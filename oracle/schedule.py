@@ -47,7 +47,7 @@ from typing import List, Optional, Tuple
 
 import numpy as np
 
-from .sampler import SET_B, SET_C
+from .sampler import SET_B, SET_C, SET_EXACT
 
 PAULI = {
     "I": np.eye(2, dtype=complex),
@@ -74,6 +74,8 @@ def setting_operator(paulis: str, theta: float, delta: float, setting: int) -> n
     P = pauli_matrix(paulis)
     if setting == SET_C:
         return -1j * P
+    if setting == SET_EXACT:
+        return math.cos(theta / 2.0) * np.eye(P.shape[0]) - 1j * math.sin(theta / 2.0) * P
     phi = math.copysign(delta, theta) if theta != 0.0 else delta
     return math.cos(phi / 2.0) * np.eye(P.shape[0]) - 1j * math.sin(phi / 2.0) * P
 
@@ -105,10 +107,13 @@ def build_schedule(problem, table, circuit, chi: Optional[int] = None) -> Tuple[
     n = problem.n_qubits
     chi = problem.chi_max if chi is None else chi
     L = table.l_eff
-    qubit_at = list(range(n))
-    site_of = list(range(n))
+    init = getattr(problem, "initial_mps", None)
+    qubit_at = list(init.qubit_at) if init is not None else list(range(n))
+    site_of = [0] * n
+    for k, q in enumerate(qubit_at):
+        site_of[q] = k
     ops: List[tuple] = []
-    centre = [0]
+    centre = [init.centre if init is not None else 0]
 
     def move_centre_to(i: int):
         # the centre must end on i or i + 1
@@ -185,7 +190,7 @@ def build_schedule(problem, table, circuit, chi: Optional[int] = None) -> Tuple[
         else:
             pa, pb = term.paulis[0], term.paulis[1]
         pending.M = U @ pending.M
-        if setting == SET_B:
+        if setting != SET_C:
             pending.has_b = True
         else:
             pending.La = PAULI[pa] @ pending.La

@@ -36,6 +36,12 @@ class tepai_pauli_string(C.Structure):
                 ("coeff", C.c_double)]
 
 
+class tepai_mps(C.Structure):
+    _fields_ = [("bond", C.POINTER(C.c_uint32)), ("tensors", C.POINTER(C.c_double)),
+                ("qubit_at", C.POINTER(C.c_uint32)), ("centre", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
 class tepai_problem(C.Structure):
     _fields_ = [("n_qubits", C.c_uint32), ("n_terms", C.c_uint32),
                 ("terms", C.POINTER(tepai_term)), ("total_time", C.c_double),
@@ -45,7 +51,8 @@ class tepai_problem(C.Structure):
                 ("chi_per_sample", C.POINTER(C.c_uint32)), ("svd_cutoff", C.c_double),
                 ("initial_bits", C.POINTER(C.c_uint8)), ("n_obs", C.c_uint32),
                 ("n_strings", C.c_uint32), ("strings", C.POINTER(tepai_pauli_string)),
-                ("precision", C.c_uint32), ("flags", C.c_uint32)]
+                ("precision", C.c_uint32), ("flags", C.c_uint32),
+                ("initial_mps", C.POINTER(tepai_mps))]
 
 
 class tepai_sample_stats(C.Structure):
@@ -179,6 +186,20 @@ class ProblemStruct:
         s.strings = C.cast(self._strings, C.POINTER(tepai_pauli_string))
         s.precision = int(precision)
         s.flags = TEPAI_NO_PI if getattr(p, "no_pi", False) else 0
+        init = getattr(p, "initial_mps", None)
+        s.initial_mps = None
+        if init is not None:
+            if len(init.tensors) != p.n_qubits or len(init.qubit_at) != p.n_qubits:
+                raise ValueError("initial_mps must hold one tensor and one qubit per site")
+            bonds = np.ascontiguousarray(init.bonds(), dtype=np.uint32)
+            packed = np.concatenate([np.ascontiguousarray(a, dtype=np.complex128).reshape(-1)
+                                     for a in init.tensors]).view(np.float64)
+            qa = np.ascontiguousarray(init.qubit_at, dtype=np.uint32)
+            self._init = (bonds, packed, qa)
+            self._mps = tepai_mps(bonds.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                  packed.ctypes.data_as(C.POINTER(C.c_double)),
+                                  qa.ctypes.data_as(C.POINTER(C.c_uint32)), int(init.centre), 0)
+            s.initial_mps = C.pointer(self._mps)
         self.struct = s
         self.n_obs = s.n_obs
 

@@ -172,6 +172,27 @@ tepai_status validate(tepai_handle* h, const tepai_problem* p) {
     }
     if (!std::isfinite(ps.coeff)) return fail(h, TEPAI_ERANGE, "non-finite string coefficient");
   }
+  if (const tepai_mps* m = p->initial_mps) {
+    if (!m->bond || !m->tensors) return fail(h, TEPAI_EINVAL, "initial_mps bond/tensors NULL");
+    if (m->bond[0] != 1 || m->bond[n] != 1) return fail(h, TEPAI_EINVAL, "initial_mps end bonds must be 1");
+    uint32_t cap = p->chi_max;
+    if (p->chi_per_sample)
+      for (uint64_t s = 0; s < p->n_samples; ++s) cap = std::min(cap, p->chi_per_sample[s]);
+    for (uint32_t k = 0; k <= n; ++k)
+      if (m->bond[k] < 1 || m->bond[k] > cap)
+        return fail(h, TEPAI_ERANGE, "initial_mps bond " + std::to_string(k) + " outside [1, smallest bond cap]");
+    if (m->centre >= n) return fail(h, TEPAI_ERANGE, "initial_mps centre out of range");
+    if (m->qubit_at) {
+      std::vector<int> seen(n, 0);
+      for (uint32_t k = 0; k < n; ++k) {
+        if (m->qubit_at[k] >= n || seen[m->qubit_at[k]]++)
+          return fail(h, TEPAI_EINVAL, "initial_mps qubit_at must be a permutation");
+      }
+    }
+    if (m->reserved != 0) return fail(h, TEPAI_EINVAL, "initial_mps reserved must be 0");
+  } else if (!p->initial_bits) {
+    return fail(h, TEPAI_EINVAL, "initial_bits NULL");
+  }
   if (p->precision != TEPAI_FP64 && p->precision != TEPAI_FP32_MIXED)
     return fail(h, TEPAI_EINVAL, "unsupported precision");
   if ((p->flags & ~(uint32_t)TEPAI_NO_PI) != 0) return fail(h, TEPAI_EINVAL, "unsupported flags");
@@ -182,9 +203,16 @@ tepai_status validate(tepai_handle* h, const tepai_problem* p) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t rows, strings, bits, caps, states, tensors, work, total;
+  size_t rows, strings, bits, caps, states, tensors, work, init, total;
   uint64_t site_stride, work_stride;
+  uint64_t init_elems;     // packed complex values of the initial MPS (0: none)
 };
+
+// bytes of the staged initial MPS: offsets, bonds, qubits, then the tensors
+static size_t init_bytes(uint32_t n, uint64_t elems) {
+  return align256(sizeof(uint64_t) * (n + 1)) + align256(sizeof(uint32_t) * (n + 1)) +
+         align256(sizeof(uint16_t) * n) + sizeof(double2) * elems;
+}
 
 Layout layout(const tepai_problem& p, uint32_t l_eff, uint32_t count) {
   Layout L{};
@@ -209,6 +237,13 @@ Layout layout(const tepai_problem& p, uint32_t l_eff, uint32_t count) {
   off = align256(off + elem * L.site_stride * p.n_qubits * count);
   L.work = off;
   off = align256(off + sizeof(double2) * L.work_stride * count);
+  L.init = off;
+  L.init_elems = 0;
+  if (p.initial_mps) {
+    for (uint32_t k = 0; k < p.n_qubits; ++k)
+      L.init_elems += 2ull * p.initial_mps->bond[k] * p.initial_mps->bond[k + 1];
+    off = align256(off + init_bytes(p.n_qubits, L.init_elems));
+  }
   L.total = off;
   return L;
 }
@@ -230,6 +265,10 @@ struct tepai_batch {
   std::vector<DevString> strings;
   std::vector<uint8_t> bits;
   std::vector<uint32_t> caps;
+  std::vector<uint64_t> init_off;
+  std::vector<uint32_t> init_bond;
+  std::vector<uint16_t> init_qubit;
+  std::vector<double2> init_tensors;
 };
 
 extern "C" {
@@ -378,7 +417,10 @@ tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_
     }
     b->strings[s] = d;
   }
-  b->bits.assign(p->initial_bits, p->initial_bits + p->n_qubits);
+  if (p->initial_bits)
+    b->bits.assign(p->initial_bits, p->initial_bits + p->n_qubits);
+  else
+    b->bits.assign(p->n_qubits, 0);
   b->caps.resize(count);
   for (uint32_t i = 0; i < count; ++i)
     b->caps[i] = p->chi_per_sample ? p->chi_per_sample[first + i] : p->chi_max;
@@ -407,6 +449,36 @@ tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_
   a.count = count;
   a.n_strings = p->n_strings;
   a.n_obs = p->n_obs;
+  a.init_tensors = nullptr;
+  a.init_off = nullptr;
+  a.init_bond = nullptr;
+  a.init_qubit = nullptr;
+  a.init_centre = 0;
+  const uint32_t n = p->n_qubits;
+  if (const tepai_mps* m = p->initial_mps) {
+    // stage the shared MPS in the batch (the caller's buffers are not kept)
+    b->init_off.resize(n + 1);
+    b->init_bond.assign(m->bond, m->bond + n + 1);
+    b->init_qubit.resize(n);
+    uint64_t off = 0;
+    for (uint32_t k = 0; k < n; ++k) {
+      b->init_off[k] = off;
+      off += 2ull * m->bond[k] * m->bond[k + 1];
+      b->init_qubit[k] = (uint16_t)(m->qubit_at ? m->qubit_at[k] : k);
+    }
+    b->init_off[n] = off;
+    b->init_tensors.resize(off);
+    std::memcpy(b->init_tensors.data(), m->tensors, sizeof(double2) * off);
+    char* base = ws + lay.init;
+    a.init_off = (const uint64_t*)base;
+    base += align256(sizeof(uint64_t) * (n + 1));
+    a.init_bond = (const uint32_t*)base;
+    base += align256(sizeof(uint32_t) * (n + 1));
+    a.init_qubit = (const uint16_t*)base;
+    base += align256(sizeof(uint16_t) * n);
+    a.init_tensors = (const double2*)base;
+    a.init_centre = m->centre;
+  }
   hipError_t e = hipMemcpyAsync(ws + lay.rows, b->rows.data(), sizeof(DevRow) * L, hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ws + lay.strings, b->strings.data(), sizeof(DevString) * b->strings.size(), hipMemcpyHostToDevice, b->stream);
@@ -414,6 +486,15 @@ tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_
     e = hipMemcpyAsync(ws + lay.bits, b->bits.data(), p->n_qubits, hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ws + lay.caps, b->caps.data(), sizeof(uint32_t) * count, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess && a.init_tensors) {
+    e = hipMemcpyAsync((void*)a.init_off, b->init_off.data(), sizeof(uint64_t) * (n + 1), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((void*)a.init_bond, b->init_bond.data(), sizeof(uint32_t) * (n + 1), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((void*)a.init_qubit, b->init_qubit.data(), sizeof(uint16_t) * n, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((void*)a.init_tensors, b->init_tensors.data(), sizeof(double2) * b->init_tensors.size(), hipMemcpyHostToDevice, b->stream);
+  }
   if (e == hipSuccess) e = launch_init(a, b->stream);
   if (e != hipSuccess) {
     delete b;

@@ -1534,20 +1534,37 @@ __global__ __launch_bounds__(NT) void init_kernel(EngineArgs a) {
   const int slot = blockIdx.x;
   SampleState* st = a.states + slot;
   TS* T = reinterpret_cast<TS*>(a.tensors) + (uint64_t)slot * a.n * a.site_stride;
-  for (int k = threadIdx.x; k < (int)a.n; k += NT) {
-    const int bit = a.init_bits[k] ? 1 : 0;
-    T[(uint64_t)k * a.site_stride + 0] = fromz<TS>(cmk(bit ? 0.0 : 1.0, 0.0));
-    T[(uint64_t)k * a.site_stride + 1] = fromz<TS>(cmk(bit ? 1.0 : 0.0, 0.0));
+  if (a.init_tensors) {
+    // every slot starts from the shared MPS (copy-on-start)
+    for (int k = 0; k < (int)a.n; ++k) {
+      const uint64_t o = a.init_off[k], len = a.init_off[k + 1] - o;
+      TS* dst = T + (uint64_t)k * a.site_stride;
+      for (uint64_t i = threadIdx.x; i < len; i += NT) {
+        const double2 v = a.init_tensors[o + i];
+        dst[i] = fromz<TS>(cmk(v.x, v.y));
+      }
+    }
+    for (int k = threadIdx.x; k <= (int)a.n; k += NT) st->bond[k] = (uint16_t)a.init_bond[k];
+    for (int k = threadIdx.x; k < (int)a.n; k += NT) st->qubit_at[k] = a.init_qubit[k];
+  } else {
+    for (int k = threadIdx.x; k < (int)a.n; k += NT) {
+      const int bit = a.init_bits[k] ? 1 : 0;
+      T[(uint64_t)k * a.site_stride + 0] = fromz<TS>(cmk(bit ? 0.0 : 1.0, 0.0));
+      T[(uint64_t)k * a.site_stride + 1] = fromz<TS>(cmk(bit ? 1.0 : 0.0, 0.0));
+    }
+    for (int k = threadIdx.x; k <= (int)a.n; k += NT) st->bond[k] = 1;
+    for (int k = threadIdx.x; k < (int)a.n; k += NT) st->qubit_at[k] = (uint16_t)k;
   }
-  for (int k = threadIdx.x; k <= (int)a.n; k += NT) st->bond[k] = 1;
-  for (int k = threadIdx.x; k < (int)a.n; k += NT) st->qubit_at[k] = (uint16_t)k;
   if (threadIdx.x == 0) {
-    st->centre = 0;
+    st->centre = a.init_tensors ? a.init_centre : 0;
     st->chi_cap = a.chi_caps[slot];
     st->sign = 1;
     st->layer = 0;
     st->flags = 0;
-    st->max_bond = 1;
+    uint32_t mb = 1;
+    if (a.init_tensors)
+      for (uint32_t k = 0; k <= a.n; ++k) mb = a.init_bond[k] > mb ? a.init_bond[k] : mb;
+    st->max_bond = mb;
     st->n_gates = st->updates = st->swap_updates = st->shifts = st->sweeps = 0;
     st->nonconverged = st->ties = 0;
     st->sum_chi3 = st->nominal_flops = st->discarded = st->max_discarded = 0.0;

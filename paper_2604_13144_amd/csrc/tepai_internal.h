@@ -74,6 +74,12 @@ struct EngineArgs {
   uint32_t n_strings;
   uint32_t n_obs;
   uint32_t mixed;         // 1: TEPAI_FP32_MIXED (complex64 site tensors)
+  // shared starting MPS (null init_tensors: computational-basis start)
+  const double2* init_tensors;   // packed site tensors, site k at init_off[k]
+  const uint64_t* init_off;      // [n + 1]
+  const uint32_t* init_bond;     // [n + 1]
+  const uint16_t* init_qubit;    // [n]
+  uint32_t init_centre;
 };
 
 // Kernel launchers (kernels.hip).

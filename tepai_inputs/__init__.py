@@ -49,6 +49,24 @@ Observable = Tuple[PauliString, ...]
 
 
 @dataclass(frozen=True)
+class InitialMPS:
+    """A shared starting state for every sample (hybrid start).
+
+    ``tensors[k]`` is the complex site tensor at chain site k, shaped
+    (chi_k, 2, chi_{k+1}) with chi_0 = chi_n = 1; ``qubit_at[k]`` is the qubit
+    held at site k; sites left of ``centre`` are left-canonical, sites right
+    of it right-canonical.
+    """
+
+    tensors: Tuple[np.ndarray, ...]
+    centre: int
+    qubit_at: Tuple[int, ...]
+
+    def bonds(self) -> Tuple[int, ...]:
+        return (1,) + tuple(int(a.shape[2]) for a in self.tensors)
+
+
+@dataclass(frozen=True)
 class Problem:
     """Everything that defines one TE-PAI estimation problem.
 
@@ -71,6 +89,7 @@ class Problem:
     svd_cutoff: float = 1e-12
     chi_per_sample: Optional[Tuple[int, ...]] = None
     no_pi: bool = False         # biased variant without pi rotations
+    initial_mps: Optional[InitialMPS] = None   # start every sample from this state
     name: str = ""
 
     def with_(self, **kw) -> "Problem":

@@ -47,6 +47,8 @@ int main(void) {
   printf("tepai_pauli_string %zu\n", sizeof(tepai_pauli_string));
   printf("tepai_problem %zu\n", sizeof(tepai_problem));
   printf("tepai_sample_stats %zu\n", sizeof(tepai_sample_stats));
+  printf("tepai_mps %zu\n", sizeof(tepai_mps));
+  P(tepai_problem, initial_mps) P(tepai_mps, qubit_at) P(tepai_mps, centre)
   P(tepai_term, coeff) P(tepai_problem, delta) P(tepai_problem, chi_per_sample)
   P(tepai_problem, strings) P(tepai_problem, flags) P(tepai_sample_stats, sign)
   P(tepai_sample_stats, flags) P(tepai_pauli_string, coeff)
@@ -61,7 +63,8 @@ int main(void) {
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
     got = dict(l.rsplit(" ", 1) for l in out.strip().splitlines())
     ct = {"tepai_term": L.tepai_term, "tepai_pauli_string": L.tepai_pauli_string,
-          "tepai_problem": L.tepai_problem, "tepai_sample_stats": L.tepai_sample_stats}
+          "tepai_problem": L.tepai_problem, "tepai_sample_stats": L.tepai_sample_stats,
+          "tepai_mps": L.tepai_mps}
     for k, v in got.items():
         if "." in k:
             s, f = k.split(".")
@@ -151,3 +154,27 @@ def test_workspace_size_scales_with_batch():
     chi, n = 128, 64
     want = 16 * (n * 2 * chi * chi + 3 * (2 * chi) ** 2)
     assert abs(per - want) / want < 0.01
+
+
+def test_initial_mps_validation_and_workspace():
+    from oracle.trotter import trotter_initial_mps
+    pre = ti.small_ring(6, seed=3, T=0.4, N=6, chi=4, n_samples=1)
+    init = trotter_initial_mps(pre, 6, 4)
+    p = pre.with_(n_samples=3, initial_mps=init)
+    L.tepai_validate(None, L.ProblemStruct(p))
+    # the workspace grows by the staged copy of the shared state
+    extra = L.tepai_workspace_size(None, L.ProblemStruct(p), 1) - \
+        L.tepai_workspace_size(None, L.ProblemStruct(p.with_(initial_mps=None)), 1)
+    assert extra >= 16 * sum(a.size for a in init.tensors)
+    # a bond above the smallest cap of the samples
+    with pytest.raises(L.TepaiError) as e:
+        L.tepai_validate(None, L.ProblemStruct(p.with_(chi_per_sample=(4, 2, 4))))
+    assert e.value.status == -2
+    # not a permutation
+    bad = ti.InitialMPS(init.tensors, init.centre, (0,) * 6)
+    with pytest.raises(L.TepaiError) as e:
+        L.tepai_validate(None, L.ProblemStruct(p.with_(initial_mps=bad)))
+    assert e.value.status == -1
+    # centre out of range
+    with pytest.raises(L.TepaiError):
+        L.tepai_validate(None, L.ProblemStruct(p.with_(initial_mps=ti.InitialMPS(init.tensors, 6, init.qubit_at))))

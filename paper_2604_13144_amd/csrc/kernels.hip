@@ -1609,112 +1609,226 @@ __global__ __launch_bounds__(NT) void evolve_kernel(EngineArgs a, uint32_t n_lay
   store_state(a, slot, sh, layer0 + n_layers);
 }
 
-// Observables of every slot: sweep the centre from site 0 to n-1; at site c
-// evaluate every Pauli string whose first site is c by a transfer-matrix
-// contraction from c (left part left-canonical) to its last site (right part
-// right-canonical), normalised by the centre's squared norm.
+// ------------------------------------------------------------ observables
+// One-site operator of a Pauli string at a site (identity if the string has
+// no factor there).
+struct Op2 {
+  z2 m[4];
+  bool id;
+};
+
+__device__ Op2 string_op(const DevString& str, int site, const Shared& sh) {
+  Op2 o;
+  o.id = true;
+  o.m[0] = cmk(1, 0);
+  o.m[1] = cmk(0, 0);
+  o.m[2] = cmk(0, 0);
+  o.m[3] = cmk(1, 0);
+  for (uint32_t t = 0; t < str.n_ops; ++t) {
+    if (sh.site_of[str.q[t]] != site) continue;
+    z2 n[4];
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 2; ++c) {
+        z2 v = cmk(0, 0);
+        for (int m = 0; m < 2; ++m) cfma(v, pauli_el(str.p[t], r, m), o.m[m * 2 + c]);
+        n[r * 2 + c] = v;
+      }
+    for (int e = 0; e < 4; ++e) o.m[e] = n[e];
+    o.id = false;
+  }
+  return o;
+}
+
+// Left environment through site A (kl x 2 x kr) with operator O:
+// E'[b'][b] = sum conj(A[a',s',b']) O[s'][s] E[a'][a] A[a,s,b]  (bra first).
+// F (kl x 2kr) is scratch; all matrices row-major in global memory.
+template <bool MIX>
+__device__ void env_left(const TSite<MIX>* A_, int kl, int kr, const z2* E_, z2* F_, z2* Eo_,
+                         const Op2& O) {
+  using TS = TSite<MIX>;
+  const glob<TS>* A = (const glob<TS>*)A_;
+  const gz2* E = (const gz2*)E_;
+  gz2* F = (gz2*)F_;
+  gz2* Eo = (gz2*)Eo_;
+  const int n2 = 2 * kr;
+  zgemm_p<MIX>(kl, n2, kl, [&](int i, int k) { return (z2)E[(uint64_t)i * kl + k]; },
+               [&](int k, int j) { return toz((TS)A[(uint64_t)k * n2 + j]); },
+               [&](int i, int j, z2 v) { F[(uint64_t)i * n2 + j] = v; });
+  __syncthreads();
+  if (!O.id) {
+    for (int idx = threadIdx.x; idx < kl * kr; idx += NT) {
+      const int a = idx / kr, b = idx - a * kr;
+      const z2 f0 = F[(uint64_t)a * n2 + b], f1 = F[(uint64_t)a * n2 + kr + b];
+      z2 g0 = cmk(0, 0), g1 = cmk(0, 0);
+      cfma(g0, O.m[0], f0);
+      cfma(g0, O.m[1], f1);
+      cfma(g1, O.m[2], f0);
+      cfma(g1, O.m[3], f1);
+      F[(uint64_t)a * n2 + b] = g0;
+      F[(uint64_t)a * n2 + kr + b] = g1;
+    }
+    __syncthreads();
+  }
+  // rows r = (a', s') of A and F, kr columns each
+  zgemm_p<MIX>(kr, kr, 2 * kl, [&](int bp, int r) { return cconj(toz((TS)A[(uint64_t)r * kr + bp])); },
+               [&](int r, int b) { return (z2)F[(uint64_t)r * kr + b]; },
+               [&](int bp, int b, z2 v) { Eo[(uint64_t)bp * kr + b] = v; });
+  __syncthreads();
+}
+
+// Right environment through site A: R'[a][a'] = sum A[a,s,b] R[b][b'] conj(A[a',s,b'])
+// (ket first).
+template <bool MIX>
+__device__ void env_right(const TSite<MIX>* A_, int kl, int kr, const z2* R_, z2* F_, z2* Ro_) {
+  using TS = TSite<MIX>;
+  const glob<TS>* A = (const glob<TS>*)A_;
+  const gz2* R = (const gz2*)R_;
+  gz2* F = (gz2*)F_;
+  gz2* Ro = (gz2*)Ro_;
+  zgemm_p<MIX>(2 * kl, kr, kr, [&](int r, int b) { return toz((TS)A[(uint64_t)r * kr + b]); },
+               [&](int b, int bp) { return (z2)R[(uint64_t)b * kr + bp]; },
+               [&](int r, int bp, z2 v) { F[(uint64_t)r * kr + bp] = v; });
+  __syncthreads();
+  const int n2 = 2 * kr;
+  zgemm_p<MIX>(kl, kl, n2, [&](int a, int j) { return (z2)F[(uint64_t)a * n2 + j]; },
+               [&](int j, int ap) { return cconj(toz((TS)A[(uint64_t)ap * n2 + j])); },
+               [&](int a, int ap, z2 v) { Ro[(uint64_t)a * kl + ap] = v; });
+  __syncthreads();
+}
+
+__device__ void set_identity(z2* M, int d) {
+  for (int idx = threadIdx.x; idx < d * d; idx += NT) M[idx] = cmk((idx / d) == (idx % d) ? 1.0 : 0.0, 0.0);
+  __syncthreads();
+}
+
+__device__ void copy_mat(z2* dst, const z2* src, int len) {
+  for (int idx = threadIdx.x; idx < len; idx += NT) dst[idx] = src[idx];
+  __syncthreads();
+}
+
+// Re sum_{b,b'} E[b'][b] R[b][b'] (R = null: the identity), all threads get it.
+__device__ double env_trace(const z2* E, const z2* R, int d, Shared& sh) {
+  double t = 0.0;
+  for (int idx = threadIdx.x; idx < d * d; idx += NT) {
+    const int bp = idx / d, b = idx - bp * d;
+    if (R) {
+      const z2 e = E[idx], r = R[(uint64_t)b * d + bp];
+      t += e.x * r.x - e.y * r.y;
+    } else if (b == bp) {
+      t += E[idx].x;
+    }
+  }
+  return block_sum(t, sh.red);
+}
+
+// Observables of every slot, contracted around the orthogonality centre c:
+// the sites left of c are left-canonical and those right of it
+// right-canonical, so the environment is the identity on the left bond of
+// any site <= c and on the right bond of any site >= c.  A Pauli string on
+// sites first..last is the transfer from an identity (or from the left
+// environment of the sweep, when first > c) through its sites with its
+// factors inserted, closed by the identity (last >= c) or by the right
+// environment of the sweep (last < c); normalised by |A_c|^2.  Transfers are
+// GEMMs on the path's matrix cores; the state is not changed.
 template <int RPL, bool MIX>
 __global__ __launch_bounds__(NT) void observe_kernel(EngineArgs a, double* values,
                                                      double* weights) {
+  using TS = TSite<MIX>;
   __shared__ Shared sh;
-  __shared__ z2 Jl[jl_size<RPL>()];
   __shared__ double acc_obs[256];
   const int slot = blockIdx.x;
-  const Slot S = make_slot<MIX>(a, slot, Jl);
+  const Slot S = make_slot<MIX>(a, slot, nullptr);
   load_state(a, slot, sh);
-  const double obs_cut = 1e-30;    // gauge-only shifts
   for (int o = threadIdx.x; o < 256; o += NT) acc_obs[o] = 0.0;
-  while (sh.centre > 0) shift_left<RPL, MIX>(S, sh.centre, obs_cut, sh);
-  z2* E = S.Y0;
-  z2* F = S.W;
-  for (int c = 0; c < (int)a.n; ++c) {
-    using TS = TSite<MIX>;
+  const int n = (int)a.n, c = sh.centre;
+  double nn = 0.0;
+  {
     const TS* Ac = site<TS>(S, c);
-    const int cl = sh.bond[c], cr = sh.bond[c + 1];
-    double nn = 0.0;
-    for (int idx = threadIdx.x; idx < cl * 2 * cr; idx += NT) {
+    const int len = sh.bond[c] * 2 * sh.bond[c + 1];
+    for (int idx = threadIdx.x; idx < len; idx += NT) {
       const z2 v = toz(Ac[idx]);
       nn += v.x * v.x + v.y * v.y;
     }
-    const double norm2 = block_sum(nn, sh.red);
+  }
+  const double norm2 = block_sum(nn, sh.red);
+  const uint64_t chi2 = (uint64_t)a.chi_max * a.chi_max;
+  z2* env = S.Y0;                  // environment of the sweep
+  z2* F = S.W;                     // GEMM scratch (chi x 2 chi)
+  z2* ea = S.P;                    // a string's environment, ping-pong
+  z2* eb = S.P + chi2;
+  z2* et = S.P + 2 * chi2;         // new sweep environment
+  const Op2 ident = {{cmk(1, 0), cmk(0, 0), cmk(0, 0), cmk(1, 0)}, true};
+
+  // value of string str from site f (environment `start` on the left bond of
+  // f, identity when null) to its last site l, closed by `close` (null: identity)
+  auto string_value = [&](const DevString& str, int f, int l, const z2* start, const z2* close) {
+    z2* cur = ea;
+    z2* nxt = eb;
+    if (start)
+      copy_mat(cur, start, sh.bond[f] * sh.bond[f]);
+    else
+      set_identity(cur, sh.bond[f]);
+    for (int k = f; k <= l; ++k) {
+      const Op2 o = string_op(str, k, sh);
+      env_left<MIX>(site<TS>(S, k), sh.bond[k], sh.bond[k + 1], cur, F, nxt, o);
+      z2* t = cur;
+      cur = nxt;
+      nxt = t;
+    }
+    return env_trace(cur, close, sh.bond[l + 1], sh);
+  };
+  auto span = [&](const DevString& str, int& f, int& l) {
+    f = n;
+    l = -1;
+    for (uint32_t t = 0; t < str.n_ops; ++t) {
+      const int q = sh.site_of[str.q[t]];
+      f = q < f ? q : f;
+      l = q > l ? q : l;
+    }
+  };
+  auto add = [&](const DevString& str, double v) {
+    if (threadIdx.x == 0) acc_obs[str.observable] += str.coeff * v / norm2;
+    __syncthreads();
+  };
+
+  // strings that start at or right of the centre: left-to-right sweep
+  set_identity(env, sh.bond[c]);
+  for (int k = c; k < n; ++k) {
     for (uint32_t si = 0; si < a.n_strings; ++si) {
       const DevString str = a.strings[si];
-      int first = (int)a.n, last = -1;
-      for (uint32_t t = 0; t < str.n_ops; ++t) {
-        const int q = sh.site_of[str.q[t]];
-        first = q < first ? q : first;
-        last = q > last ? q : last;
-      }
-      if (first != c) continue;
-      // E = identity on the left bond of site c
-      int dl = cl;
-      for (int idx = threadIdx.x; idx < dl * dl; idx += NT)
-        E[idx] = cmk((idx / dl) == (idx % dl) ? 1.0 : 0.0, 0.0);
-      __syncthreads();
-      for (int k = c; k <= last; ++k) {
-        const TS* A = site<TS>(S, k);
-        const int kl = sh.bond[k], kr = sh.bond[k + 1];
-        // operator on this site (product of the string's factors here)
-        z2 O[4] = {cmk(1, 0), cmk(0, 0), cmk(0, 0), cmk(1, 0)};
-        for (uint32_t t = 0; t < str.n_ops; ++t) {
-          if (sh.site_of[str.q[t]] != k) continue;
-          z2 On[4];
-          for (int r = 0; r < 2; ++r)
-            for (int cc = 0; cc < 2; ++cc) {
-              z2 v = cmk(0, 0);
-              for (int m = 0; m < 2; ++m) cfma(v, pauli_el(str.p[t], r, m), O[m * 2 + cc]);
-              On[r * 2 + cc] = v;
-            }
-          for (int e = 0; e < 4; ++e) O[e] = On[e];
-        }
-        // F[a', s, b] = sum_a E[a', a] A[a, s, b]
-        for (int idx = threadIdx.x; idx < kl * 2 * kr; idx += NT) {
-          const int ap = idx / (2 * kr), sb = idx - ap * 2 * kr;
-          z2 v = cmk(0, 0);
-          for (int aa = 0; aa < kl; ++aa) cfma(v, E[ap * kl + aa], toz(A[(uint64_t)aa * 2 * kr + sb]));
-          F[idx] = v;
-        }
-        __syncthreads();
-        // E'[b', b] = sum_{a', s', s} conj(A[a', s', b']) O[s', s] F[a', s, b]
-        for (int idx = threadIdx.x; idx < kr * kr; idx += NT) {
-          const int bp = idx / kr, b = idx - bp * kr;
-          z2 v = cmk(0, 0);
-          for (int ap = 0; ap < kl; ++ap) {
-            const z2 f0 = F[(uint64_t)ap * 2 * kr + 0 * kr + b];
-            const z2 f1 = F[(uint64_t)ap * 2 * kr + 1 * kr + b];
-            z2 of0 = cmk(0, 0), of1 = cmk(0, 0);
-            cfma(of0, O[0], f0);
-            cfma(of0, O[1], f1);
-            cfma(of1, O[2], f0);
-            cfma(of1, O[3], f1);
-            cfmac(v, toz(A[(uint64_t)ap * 2 * kr + 0 * kr + bp]), of0);
-            cfmac(v, toz(A[(uint64_t)ap * 2 * kr + 1 * kr + bp]), of1);
-          }
-          F[kl * 2 * kr + idx] = v;     // stage after F's live part
-        }
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < kr * kr; idx += NT) E[idx] = F[kl * 2 * kr + idx];
-        __syncthreads();
-        dl = kr;
-      }
-      double tr = 0.0;
-      for (int b = threadIdx.x; b < dl; b += NT) tr += E[b * dl + b].x;
-      tr = block_sum(tr, sh.red);
-      if (threadIdx.x == 0) acc_obs[str.observable] += str.coeff * tr / norm2;
-      __syncthreads();
+      int f, l;
+      span(str, f, l);
+      if (f == k) add(str, string_value(str, f, l, env, nullptr));
     }
-    if (c + 1 < (int)a.n) shift_right<RPL, MIX>(S, c, obs_cut, sh);
+    if (k + 1 < n) {
+      env_left<MIX>(site<TS>(S, k), sh.bond[k], sh.bond[k + 1], env, F, et, ident);
+      copy_mat(env, et, sh.bond[k + 1] * sh.bond[k + 1]);
+    }
+  }
+  // strings that start left of the centre and reach it: identity at both ends
+  for (uint32_t si = 0; si < a.n_strings; ++si) {
+    const DevString str = a.strings[si];
+    int f, l;
+    span(str, f, l);
+    if (f < c && l >= c) add(str, string_value(str, f, l, nullptr, nullptr));
+  }
+  // strings that end left of the centre: right-to-left sweep of R
+  set_identity(env, sh.bond[c + 1]);
+  for (int k = c; k >= 1; --k) {
+    env_right<MIX>(site<TS>(S, k), sh.bond[k], sh.bond[k + 1], env, F, et);
+    copy_mat(env, et, sh.bond[k] * sh.bond[k]);          // R on the left bond of k
+    for (uint32_t si = 0; si < a.n_strings; ++si) {
+      const DevString str = a.strings[si];
+      int f, l;
+      span(str, f, l);
+      if (l == k - 1) add(str, string_value(str, f, l, nullptr, env));
+    }
   }
   __syncthreads();
   const SampleState* st = a.states + slot;
   for (uint32_t o = threadIdx.x; o < a.n_obs; o += NT)
     values[(uint64_t)slot * a.n_obs + o] = acc_obs[o];
-  if (threadIdx.x == 0) {
-    weights[slot] = (double)st->sign * exp((double)st->layer * a.log_g1_step);
-    a.states[slot].centre = sh.centre;
-    a.states[slot].shifts = sh.shifts;
-  }
-  for (int k = threadIdx.x; k <= (int)a.n; k += NT) a.states[slot].bond[k] = sh.bond[k];
+  if (threadIdx.x == 0) weights[slot] = (double)st->sign * exp((double)st->layer * a.log_g1_step);
 }
 
 // Weighted reduction: one block per observable, fixed summation order.

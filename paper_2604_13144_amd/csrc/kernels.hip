@@ -237,7 +237,10 @@ struct Shared {
   uint16_t perm[2 * kMaxChi]; // columns by descending norm
   uint16_t order[2 * kMaxChi];// Jacobi sweep order
   uint16_t piv[2 * kMaxChi];  // column pivots of the QR preconditioner
-  int qr_p;
+  double qr_vn0[2 * kMaxChi]; // QR: column norms at the start of the panel
+  z2 qr_t[32];                // QR: u_k^H u_i for the panel's reflectors i < k
+  z2 qr_w[32];                // QR: W_i(pivot column) of the panel's reflectors
+  int qr_p, qr_mark, qr_done;
   double qr_v, qr_k;
   uint16_t bond[kMaxQubits + 1];
   uint16_t qubit_at[kMaxQubits];
@@ -817,157 +820,280 @@ __device__ __forceinline__ void zgemm_p(int M, int N, int K, const FA& fa, const
 // Z P = Q Rz.  On return the upper trapezoid of Z holds Rz and sh.piv[j] is
 // the original index of the column at position j; Q is not formed and the
 // part below the diagonal is scratch.  Step j takes as pivot the remaining
-// column with the largest norm below row j (lowest index on ties); those
-// norms are recomputed from the updated columns in the same pass that applies
-// the reflector, so no norm downdating is needed.  The reflector for
-// x = Z[j:, j], x_0 = |x_0| e^{i phi}: beta = -e^{i phi} |x|, u = x - beta e_0,
-// H = I - kappa u u^H with kappa = 1 / (|x| (|x| + |x_0|)); H is unitary and
-// Hermitian and maps x to beta e_0, so H y = y - kappa (u^H y) u.
-template <int RPL, typename TZ>
-__device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_, z2* dummy_) {
+// column with the largest norm below row j (lowest index on ties).  The
+// reflector for x = Z[j:, j], x_0 = |x_0| e^{i phi}: beta = -e^{i phi} |x|,
+// u = x - beta e_0, H = I - kappa u u^H with kappa = 1 / (|x| (|x| + |x_0|));
+// H is unitary and Hermitian and maps x to beta e_0.
+//
+// The trailing columns are updated lazily, in panels of up to 32 steps (the
+// blocked pivoted QR of LAPACK's xLAQPS): with u_i and W_i(c) = kappa_i u_i^H
+// (column c after reflectors < i) kept for the panel's steps, the current
+// column c is Z0_c - sum_i u_i W_i(c), where Z0 is the matrix at the start
+// of the panel.  Step k forms W_k(c) = kappa_k (u_k^H Z0_c - sum_{i<k}
+// (u_k^H u_i) W_i(c)) in one read-only pass, writes the new row k of R and
+// downdates the squared norms by its entries; the matrix itself is updated
+// once per panel (one GEMM).  A panel ends early when a downdated norm has
+// lost more than six digits, and every panel starts from exact norms, so
+// no pivot is chosen on a norm that cancellation has spoiled.  u_i live in
+// LDS (Ul), W_i(c) in global scratch (Wb, nb x nc).
+template <int RPL>
+__device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_, z2* Wb_) {
   constexpr int E = 4 * RPL;
-  glob<TZ>* Z = (glob<TZ>*)Z_;
+  gz2* Z = (gz2*)Z_;
   lz2* Ul = (lz2*)Ul_;
+  gz2* Wb = (gz2*)Wb_;
   ld* vn = (ld*)sh.sig2;
+  ld* vn0 = (ld*)sh.qr_vn0;
   const int l16 = threadIdx.x & 15, row = threadIdx.x >> 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int eall = (nr + 15) >> 4;
-#pragma unroll 1
-  for (int i = row; i < nc; i += NROWS) {
-    const glob<TZ>* col = Z + (uint64_t)i * nr;
-    double a = 0.0;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int r = l16 + 16 * e;
-      if (e < eall && r < nr) {
-        const z2 v = toz((TZ)col[r]);
-        a = fma(v.x, v.x, fma(v.y, v.y, a));
-      }
-    }
-    a = row16_sum(a);
-    if (l16 == 0) vn[i] = a;
-  }
-  for (int i = threadIdx.x; i < nc; i += NT) sh.piv[i] = (uint16_t)i;
-  __syncthreads();
   const int m = nr < nc ? nr : nc;
+  const int nbmax = (jl_size<RPL>() / nr) < 32 ? (jl_size<RPL>() / nr) : 32;
+
+  // exact squared norms of rows r0.. of columns r0.. (all rows read, in-bounds)
+  auto exact_norms = [&](int r0) {
 #pragma unroll 1
-  for (int j = 0; j < m; ++j) {
-    if (wv == 0) {
-      double best = -1.0;
-      int bi = nc;
-      for (int i = j + lane; i < nc; i += 64) {
-        const double v = vn[i];
-        if (v > best) {
-          best = v;
-          bi = i;
-        }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      if (lane == 0) {
-        sh.qr_p = bi;
-        sh.qr_v = best;
-      }
-    }
-    __syncthreads();
-    const int p = sh.qr_p;
-    if (!(sh.qr_v > 0.0)) break;      // every remaining column is zero
-    if (p != j) {
-      glob<TZ>* a = Z + (uint64_t)j * nr;
-      glob<TZ>* b = Z + (uint64_t)p * nr;
-      for (int r = threadIdx.x; r < nr; r += NT) {
-        const TZ t = a[r];
-        a[r] = b[r];
-        b[r] = t;
-      }
-      if (threadIdx.x == 0) {
-        const double t = vn[j];
-        vn[j] = vn[p];
-        vn[p] = t;
-        const uint16_t q = sh.piv[j];
-        sh.piv[j] = sh.piv[p];
-        sh.piv[p] = q;
-      }
-    }
-    __syncthreads();
-    if (wv == 0) {
-      glob<TZ>* col = Z + (uint64_t)j * nr;
-      const z2 a0 = toz((TZ)col[j]);
-      const double aa = sqrt(a0.x * a0.x + a0.y * a0.y);
-      const double xn = sqrt(vn[j]);
-      const z2 ph = aa > 0.0 ? cmk(a0.x / aa, a0.y / aa) : cmk(1.0, 0.0);
-      for (int r = j + lane; r < nr; r += 64)
-        Ul[r] = r == j ? cmk(ph.x * (aa + xn), ph.y * (aa + xn)) : toz((TZ)col[r]);
-      if (lane == 0) {
-        col[j] = fromz<TZ>(cmk(-ph.x * xn, -ph.y * xn));
-        sh.qr_k = 1.0 / (xn * (xn + aa));
-      }
-    }
-    __syncthreads();
-    const double kap = sh.qr_k;
-    // elements e < ea of a lane hold rows j + l16 + 16 e < nr; the passes run
-    // over groups of four elements behind a uniform bound, with in-bounds
-    // (clamped) loads and stores past the column sent to a per-lane dummy
-    // slot, so each group is straight-line code
-    const int ea = (nr - j + 15) >> 4;
-    z2 uv[E];
-#pragma unroll
-    for (int g = 0; g < E / 4; ++g) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = 4 * g + q, r = j + l16 + 16 * e;
-        const z2 u = (4 * g < ea) ? (z2)Ul[r < nr ? r : nr - 1] : cmk(0.0, 0.0);
-        uv[e] = r < nr ? u : cmk(0.0, 0.0);
-      }
-    }
-    glob<TZ>* dummy = (glob<TZ>*)dummy_ + threadIdx.x;
-#pragma unroll 1
-    for (int i = j + 1 + row; i < nc; i += NROWS) {
-      glob<TZ>* col = Z + (uint64_t)i * nr;
-      z2 z[E];
-      double gr = 0.0, gi = 0.0;
-#pragma unroll
-      for (int g = 0; g < E / 4; ++g) {
-        if (4 * g < ea) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int e = 4 * g + q, r = j + l16 + 16 * e;
-            const z2 v = toz((TZ)col[r < nr ? r : nr - 1]);
-            z[e] = r < nr ? v : cmk(0.0, 0.0);
-            gr = fma(uv[e].x, z[e].x, fma(uv[e].y, z[e].y, gr));
-            gi = fma(uv[e].x, z[e].y, fma(-uv[e].y, z[e].x, gi));
-          }
-        }
-      }
-      gr = row16_sum(gr) * kap;
-      gi = row16_sum(gi) * kap;
+    for (int i = r0 + row; i < nc; i += NROWS) {
+      const gz2* col = Z + (uint64_t)i * nr;
       double a = 0.0;
 #pragma unroll
-      for (int g = 0; g < E / 4; ++g) {
-        if (4 * g < ea) {
+      for (int e = 0; e < E; ++e) {
+        const int r = r0 + l16 + 16 * e;
+        const z2 v = col[r < nr ? r : nr - 1];
+        const double w = r < nr ? 1.0 : 0.0;
+        a = fma(w * v.x, v.x, fma(w * v.y, v.y, a));
+      }
+      a = row16_sum(a);
+      if (l16 == 0) {
+        vn[i] = a;
+        vn0[i] = a;
+      }
+    }
+  };
+  exact_norms(0);
+  for (int i = threadIdx.x; i < nc; i += NT) sh.piv[i] = (uint16_t)i;
+  if (threadIdx.x == 0) sh.qr_done = 0;
+  __syncthreads();
+
+#pragma unroll 1
+  for (int j0 = 0; j0 < m;) {
+    const int kmax = (m - j0) < nbmax ? (m - j0) : nbmax;
+    if (threadIdx.x == 0) sh.qr_mark = 0;
+    __syncthreads();
+    int kb = 0;
+#pragma unroll 1
+    for (int k = 0; k < kmax; ++k) {
+      const int j = j0 + k;
+      if (wv == 0) {
+        double best = -1.0;
+        int bi = nc;
+        for (int i = j + lane; i < nc; i += 64) {
+          const double v = vn[i];
+          if (v > best) {
+            best = v;
+            bi = i;
+          }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          const double ob = __shfl_xor(best, off, 64);
+          const int oi = __shfl_xor(bi, off, 64);
+          if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+          }
+        }
+        if (lane == 0) {
+          sh.qr_p = bi;
+          sh.qr_v = best;
+          if (!(best > 0.0) && k == 0) sh.qr_done = 1;   // exact norms: the rest is zero
+        }
+      }
+      __syncthreads();
+      const int p = sh.qr_p;
+      if (!(sh.qr_v > 0.0)) break;     // (downdated norms: re-check after the update)
+      if (p != j) {
+        gz2* a = Z + (uint64_t)j * nr;
+        gz2* b = Z + (uint64_t)p * nr;
+        for (int r = threadIdx.x; r < nr; r += NT) {
+          const z2 t = a[r];
+          a[r] = b[r];
+          b[r] = t;
+        }
+        for (int i = threadIdx.x; i < k; i += NT) {
+          const z2 t = Wb[(uint64_t)i * nc + j];
+          Wb[(uint64_t)i * nc + j] = Wb[(uint64_t)i * nc + p];
+          Wb[(uint64_t)i * nc + p] = t;
+        }
+        if (threadIdx.x == 0) {
+          double t = vn[j];
+          vn[j] = vn[p];
+          vn[p] = t;
+          t = vn0[j];
+          vn0[j] = vn0[p];
+          vn0[p] = t;
+          const uint16_t q = sh.piv[j];
+          sh.piv[j] = sh.piv[p];
+          sh.piv[p] = q;
+        }
+      }
+      if (threadIdx.x < k) sh.qr_w[threadIdx.x] = Wb[(uint64_t)threadIdx.x * nc + j];
+      __syncthreads();
+      // the pivot column brought up to date, and its reflector (wave 0)
+      if (wv == 0) {
+        const gz2* col = Z + (uint64_t)j * nr;
+        z2 v[RPL];
+        double x2 = 0.0;
+        z2 alpha = cmk(0.0, 0.0);
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) {
+          const int r = lane + 64 * e;
+          z2 t = (r >= j && r < nr) ? (z2)col[r] : cmk(0.0, 0.0);
+          if (r >= j && r < nr) {
+            for (int i = 0; i < k; ++i) {
+              const z2 ui = Ul[i * nr + r], wi = sh.qr_w[i];
+              t = cmk(t.x - (ui.x * wi.x - ui.y * wi.y), t.y - (ui.x * wi.y + ui.y * wi.x));
+            }
+          }
+          v[e] = t;
+          x2 = fma(t.x, t.x, fma(t.y, t.y, x2));
+          if (r == j) alpha = t;
+        }
+        x2 = wave_sum(x2);
+        alpha.x = wave_sum(alpha.x);      // one lane holds it, the others hold 0
+        alpha.y = wave_sum(alpha.y);
+        const double aa = sqrt(alpha.x * alpha.x + alpha.y * alpha.y);
+        const double xn = sqrt(x2);
+        const z2 ph = aa > 0.0 ? cmk(alpha.x / aa, alpha.y / aa) : cmk(1.0, 0.0);
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) {
+          const int r = lane + 64 * e;
+          if (r < nr) Ul[k * nr + r] = r < j ? cmk(0.0, 0.0) : (r == j ? cmk(ph.x * (aa + xn), ph.y * (aa + xn)) : v[e]);
+        }
+        if (lane == 0) {
+          Z[(uint64_t)j * nr + j] = cmk(-ph.x * xn, -ph.y * xn);
+          sh.qr_k = xn > 0.0 ? 1.0 / (xn * (xn + aa)) : 0.0;
+        }
+      }
+      __syncthreads();
+      // t_i = u_k^H u_i for the panel's earlier reflectors
+      if (row < k) {
+        double tr = 0.0, ti = 0.0;
+        for (int r = j + l16; r < nr; r += 16) {
+          const z2 a = Ul[k * nr + r], b = Ul[row * nr + r];
+          tr = fma(a.x, b.x, fma(a.y, b.y, tr));
+          ti = fma(a.x, b.y, fma(-a.y, b.x, ti));
+        }
+        tr = row16_sum(tr);
+        ti = row16_sum(ti);
+        if (l16 == 0) sh.qr_t[row] = cmk(tr, ti);
+      }
+      __syncthreads();
+      // trailing columns: W_k(c), the new row j of R, downdated norms (read-only pass)
+      {
+        const double kap = sh.qr_k;
+        const int ea = (nr - j + 15) >> 4;
+        z2 uv[E];
+#pragma unroll
+        for (int g = 0; g < E / 4; ++g) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int e = 4 * g + q, r = j + l16 + 16 * e;
-            const z2 u = uv[e];
-            const z2 v = cmk(z[e].x - (gr * u.x - gi * u.y), z[e].y - (gr * u.y + gi * u.x));
-            glob<TZ>* dst = r < nr ? col + r : dummy;
-            *dst = fromz<TZ>(v);
-            const double w = r > j ? 1.0 : 0.0;     // row j leaves the norm
-            a = fma(w * v.x, v.x, fma(w * v.y, v.y, a));
+            const z2 u = (4 * g < ea) ? (z2)Ul[k * nr + (r < nr ? r : nr - 1)] : cmk(0.0, 0.0);
+            uv[e] = r < nr ? u : cmk(0.0, 0.0);
+          }
+        }
+        // two columns per row at a time (independent loads and reductions in flight)
+        const z2 t0 = l16 < k ? sh.qr_t[l16] : cmk(0.0, 0.0);
+        const z2 t1 = l16 + 16 < k ? sh.qr_t[l16 + 16] : cmk(0.0, 0.0);
+        const z2 u0 = l16 < k ? (z2)Ul[l16 * nr + j] : cmk(0.0, 0.0);
+        const z2 u1 = l16 + 16 < k ? (z2)Ul[(l16 + 16) * nr + j] : cmk(0.0, 0.0);
+        const z2 uk = Ul[k * nr + j];
+#pragma unroll 1
+        for (int cb = j + 1 + row; cb < nc; cb += 2 * NROWS) {
+          int cc[2];
+          cc[0] = cb;
+          cc[1] = cb + NROWS;
+          double gr[2], gi[2], tr[2], ti[2], ur[2], ui[2];
+          z2 z0[2];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const bool live = cc[h] < nc;
+            const int c = live ? cc[h] : cb;            // a dead half reads column cb again
+            const gz2* col = Z + (uint64_t)c * nr;
+            // the panel's W_i(c), i < k, spread over the row's lanes (two per lane)
+            z2 w0 = cmk(0.0, 0.0), w1 = cmk(0.0, 0.0);
+            if (l16 < k) w0 = Wb[(uint64_t)l16 * nc + c];
+            if (l16 + 16 < k) w1 = Wb[(uint64_t)(l16 + 16) * nc + c];
+            double a = 0.0, b = 0.0;
+            z0[h] = cmk(0.0, 0.0);
+#pragma unroll
+            for (int g = 0; g < E / 4; ++g) {
+              if (4 * g < ea) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                  const int e = 4 * g + q, r = j + l16 + 16 * e;
+                  const z2 v0 = col[r < nr ? r : nr - 1];
+                  const z2 v = r < nr ? v0 : cmk(0.0, 0.0);
+                  if (e == 0) z0[h] = v;
+                  a = fma(uv[e].x, v.x, fma(uv[e].y, v.y, a));
+                  b = fma(uv[e].x, v.y, fma(-uv[e].y, v.x, b));
+                }
+              }
+            }
+            gr[h] = a;
+            gi[h] = b;
+            // sum_{i<k} t_i W_i(c) and sum_{i<k} u_i[j] W_i(c)
+            tr[h] = t0.x * w0.x - t0.y * w0.y + t1.x * w1.x - t1.y * w1.y;
+            ti[h] = t0.x * w0.y + t0.y * w0.x + t1.x * w1.y + t1.y * w1.x;
+            ur[h] = u0.x * w0.x - u0.y * w0.y + u1.x * w1.x - u1.y * w1.y;
+            ui[h] = u0.x * w0.y + u0.y * w0.x + u1.x * w1.y + u1.y * w1.x;
+          }
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            gr[h] = row16_sum(gr[h]);
+            gi[h] = row16_sum(gi[h]);
+            tr[h] = row16_sum(tr[h]);
+            ti[h] = row16_sum(ti[h]);
+            ur[h] = row16_sum(ur[h]);
+            ui[h] = row16_sum(ui[h]);
+          }
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int c = cc[h];
+            if (l16 == 0 && c < nc) {
+              // W_k(c) = kappa (u_k^H Z0_c - sum_{i<k} t_i W_i(c)); z0 = Z0[j, c]
+              const z2 w = cscale(cmk(gr[h] - tr[h], gi[h] - ti[h]), kap);
+              const z2 nrow = cmk(z0[h].x - ur[h] - (uk.x * w.x - uk.y * w.y),
+                                  z0[h].y - ui[h] - (uk.x * w.y + uk.y * w.x));
+              Wb[(uint64_t)k * nc + c] = w;
+              Z[(uint64_t)c * nr + j] = nrow;          // row j of R
+              const double nv = vn[c] - (nrow.x * nrow.x + nrow.y * nrow.y);
+              vn[c] = nv;
+              if (!(nv > 1e-6 * vn0[c])) sh.qr_mark = 1;
+            }
           }
         }
       }
-      a = row16_sum(a);
-      if (l16 == 0) vn[i] = a;
+      __syncthreads();
+      ++kb;
+      if (sh.qr_mark) break;
     }
+    // apply the panel's kb reflectors to rows and columns from r0 = j0 + kb on
+    const int r0 = j0 + kb;
+    if (kb > 0 && r0 < nc && r0 < nr) {
+      zgemm(nr - r0, nc - r0, kb, [&](int r, int i) { return (z2)Ul[i * nr + r0 + r]; },
+            [&](int i, int c) { return (z2)Wb[(uint64_t)i * nc + r0 + c]; },
+            [&](int r, int c, z2 v) {
+              gz2* at = Z + (uint64_t)(r0 + c) * nr + r0 + r;
+              const z2 o = *at;
+              *at = cmk(o.x - v.x, o.y - v.y);
+            });
+      __syncthreads();
+    }
+    if (r0 < nc) exact_norms(r0 < nr ? r0 : nr);
     __syncthreads();
+    j0 = r0;
+    if (sh.qr_done) break;
   }
 }
 
@@ -1002,7 +1128,7 @@ __device__ int svd_cols(z2* W, const z2* Y0, z2* X, int R, int C, Shared& sh, z2
     Z[(uint64_t)r * C + c] = fromz<TZ>(cconj(Y0[idx]));
   }
   __syncthreads();
-  qrcp<RPL, TZ>(W, C, R, sh, Jl, X);      // X is free until the QR is done
+  qrcp<RPL>(W, C, R, sh, Jl, X);      // X holds the QR's panel coefficients until it is built
   const int m = R < C ? R : C;
   for (int idx = threadIdx.x; idx < R * m; idx += NT) {
     const int jj = idx / R, r = idx - jj * R;

@@ -72,6 +72,13 @@ def parse():
                     help="comma list of paths to time (the first one gives value)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (counter calibration) and exit")
+    ap.add_argument("--workload", choices=("throughput", "truncation"), default="throughput",
+                    help="truncation: the chi = 2 vs 16 robustness experiment instead of "
+                         "the throughput step")
+    ap.add_argument("--read-every", type=int, default=100,
+                    help="truncation workload: Trotter steps between read-outs")
+    ap.add_argument("--delta-log2", type=int, default=12,
+                    help="truncation workload: PAI angle Delta = pi / 2^k")
     return ap.parse_args()
 
 
@@ -197,6 +204,100 @@ def run_path(L, h, p, precision, J, K, W, B):
     }
 
 
+def truncation_experiment(L, h, read_every, delta_log2=12):
+    """The truncation-robustness experiment on the GPU (FP64 path).
+
+    For each method (the deterministic product formula, one circuit; TE-PAI,
+    N_s = 100 circuits) and bond cap chi in {2, 16}, every sample runs the
+    n = 20, J = 1 ring to T = 1 (N = 2000) and the estimator of X_i, Y_i, Z_i
+    on every qubit is read out every `read_every` steps.  The truncation error
+    of a method at time t is the mean over the 60 observables of
+    |<O>_{chi=2}(t) - <O>_{chi=16}(t)|; TE-PAI runs the same circuits at both
+    caps (the sampler does not depend on chi), so the difference holds no
+    sampling noise between the two caps.
+    """
+    import numpy as np
+    import torch
+    import tepai_inputs as ti
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    for method in ("trotter", "tepai"):
+        for chi in (2, 16):
+            p = ti.truncation_workload(chi, trotter=method == "trotter",
+                                       delta=math.pi / 2 ** delta_log2)
+            if read_every < 1 or p.trotter_steps % read_every:
+                raise SystemExit("--read-every must divide N = %d" % p.trotter_steps)
+            ps = L.ProblemStruct(p)
+            B, n_obs = p.n_samples, ps.n_obs
+            b = L.Batch(h, ps, 0, B, stream=stream)
+            vals = torch.empty(B * n_obs, dtype=torch.float64, device=dev)
+            wts = torch.empty(B, dtype=torch.float64, device=dev)
+            mean = torch.empty(n_obs, dtype=torch.float64, device=dev)
+            se = torch.empty(n_obs, dtype=torch.float64, device=dev)
+            series, errs, steps, xs = [], [], [], []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for j in range(read_every, p.trotter_steps + 1, read_every):
+                b.evolve(read_every)
+                b.observe(vals, wts)
+                L.tepai_reduce(h, B, n_obs, vals, wts, mean, se, stream)
+                series.append(mean.cpu().numpy())
+                x = vals.view(B, n_obs) * wts.view(B, 1)          # weighted sample values
+                xs.append(x.cpu().numpy())
+                errs.append(se.cpu().numpy())
+                steps.append(j)
+                print(f"[bench] truncation {method} chi={chi}: step {j}/{p.trotter_steps}",
+                      file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            st = b.stats()
+            out[(method, chi)] = {"mean": np.array(series), "std_err": np.array(errs),
+                                  "x": np.array(xs),
+                                  "steps": steps, "wall_s": wall, "T": p.total_time,
+                                  "N": p.trotter_steps,
+                                  "gates_per_sample": float(np.mean(st["n_gates"])),
+                                  "updates_per_sample": float(np.mean(st["updates"])),
+                                  "max_bond": int(np.max(st["max_bond"])),
+                                  "discarded_per_sample": float(np.mean(st["discarded"]))}
+            print(f"[bench] truncation {method} chi={chi}: {wall:.1f} s", file=sys.stderr, flush=True)
+            b.close()
+    r = out[("trotter", 2)]
+    times = [j * r["T"] / r["N"] for j in r["steps"]]
+
+    def trunc_err(method):
+        return np.mean(np.abs(out[(method, 2)]["mean"] - out[(method, 16)]["mean"]), axis=1)
+
+    et, ep = trunc_err("trotter"), trunc_err("tepai")
+    ref = out[("trotter", 16)]["mean"]
+    tepai2_vs_ref = np.mean(np.abs(out[("tepai", 2)]["mean"] - ref), axis=1)
+    gap16 = np.mean(np.abs(out[("tepai", 16)]["mean"] - ref), axis=1)
+    se16 = np.mean(out[("tepai", 16)]["std_err"], axis=1)
+    # cancellation across the ensemble: error of the mean over the mean of the
+    # per-sample errors of the weighted values w_s <O>_s (1 = no cancellation)
+    dx = out[("tepai", 2)]["x"] - out[("tepai", 16)]["x"]          # [t, s, o]
+    per_sample = np.mean(np.abs(dx), axis=(1, 2))
+    of_mean = np.mean(np.abs(np.mean(dx, axis=1)), axis=1)
+    return {
+        "workload": "truncation: n=20 ring J=1 omega~U[-1,1], T=1, N=2000, Delta=pi/2^%d, "
+                    "N_s=100, start |+..+-+..+>, X/Y/Z of every qubit, chi in {2,16}" % delta_log2,
+        "dtype": "f64",
+        "data": "synthetic",
+        "times": times,
+        "trotter_truncation_error": et.tolist(),
+        "tepai_truncation_error": ep.tolist(),
+        "tepai_below_trotter_fraction": float(np.mean(ep < et)),
+        "mean_error_ratio_tepai_over_trotter": float(np.mean(ep) / np.mean(et)),
+        "tepai_chi2_vs_trotter_chi16": tepai2_vs_ref.tolist(),
+        "tepai_chi16_vs_trotter_chi16": gap16.tolist(),
+        "tepai_chi16_mean_std_err": se16.tolist(),
+        "tepai_per_sample_truncation_error": per_sample.tolist(),
+        "tepai_cancellation_ratio": (of_mean / np.maximum(per_sample, 1e-300)).tolist(),
+        "runs": {f"{m}_chi{c}": {k: v for k, v in d.items() if k not in ("mean", "std_err", "steps", "x")}
+                 for (m, c), d in out.items()},
+    }
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -204,6 +305,12 @@ def main():
         sys.exit(2)
     if a.copy_probe:
         copy_probe(a.copy_probe)
+        return
+    if a.workload == "truncation":
+        import torch
+        torch.cuda.init()
+        from paper_2604_13144_amd import _lib as L
+        print(json.dumps(truncation_experiment(L, L.Handle(0), a.read_every, a.delta_log2)))
         return
     import numpy as np
     import torch

@@ -70,6 +70,15 @@ enum { TEPAI_SET_A = 0, TEPAI_SET_B = 1, TEPAI_SET_C = 2 };
  *   all weights are 1, at a per-gate bias |theta| (Delta - |theta|) / 2
  *   R''(0) + O(Delta^3). */
 enum { TEPAI_NO_PI = 1u };
+/* TEPAI_TROTTER: the deterministic first-order product formula (eq.
+ *   Trotter-Suzuki) run through the same MPS engine, the comparison circuit of
+ *   sec. "Truncation": every rotation of every step is applied exactly as
+ *   R_k(theta_k) (a split rotation as its m equal sub-rotations), so every
+ *   sample is the same circuit.  The table reports gamma = (0, 1, 0),
+ *   thresholds (0, 2^63) and log_g1_step = 0: the sampler marks every rotation
+ *   TEPAI_SET_B (here meaning the exact rotation), every sign is +1 and every
+ *   weight is 1.  Cannot be combined with TEPAI_NO_PI. */
+enum { TEPAI_TROTTER = 2u };
 
 /* Storage / arithmetic precision of the MPS path.
  * TEPAI_FP64: complex128 site tensors and FP64 throughout; per-sample values
@@ -143,7 +152,7 @@ typedef struct {
   uint32_t n_strings;
   const tepai_pauli_string* strings;
   uint32_t precision;           /* TEPAI_FP64 or TEPAI_FP32_MIXED */
-  uint32_t flags;               /* 0 or TEPAI_NO_PI */
+  uint32_t flags;               /* 0, TEPAI_NO_PI or TEPAI_TROTTER */
   const tepai_mps* initial_mps; /* NULL: start from initial_bits */
 } tepai_problem;
 

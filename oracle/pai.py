@@ -107,7 +107,12 @@ def build_table(problem) -> Table:
             m = int(math.ceil(abs(theta) / delta))
             n_split += 1
         sub = theta / m
-        if getattr(problem, "no_pi", False):
+        if getattr(problem, "trotter", False):
+            # deterministic product formula (eq. Trotter-Suzuki): each rotation is
+            # always present and exact; read as the one-setting table (0, 1, 0)
+            g = (0.0, 1.0, 0.0)
+            row = Row(term=k, theta=sub, gamma=g, norm1=1.0, p=g, t1=0, t2=T_ONE)
+        elif getattr(problem, "no_pi", False):
             # probabilities are the coefficients themselves; C is never drawn
             g = gammas_no_pi(abs(sub), delta)
             row = Row(term=k, theta=sub, gamma=g, norm1=1.0, p=g,

@@ -2,7 +2,9 @@
 
 For each sample: sample the circuit, build its MPS schedule, run the MPS,
 read out <O> for every observable; then weight and reduce (protocol steps
-1-3 of the paper's sec. "TE-PAI"; estimator of Statement 2).
+1-3 of the paper's sec. "TE-PAI"; estimator of Statement 2).  A problem with
+``trotter`` set runs the deterministic product formula instead, every sample
+the same circuit with weight 1.
 """
 from __future__ import annotations
 
@@ -16,6 +18,7 @@ from .estimator import estimate, weights
 from .mps import MPS, Stats
 from .sampler import sample_circuit
 from .schedule import PAULI, build_schedule
+from .trotter import product_formula_circuit
 
 
 @dataclass
@@ -58,7 +61,11 @@ def observable_value(mps: MPS, qubit_at, observable) -> float:
 
 
 def run_sample(problem, table, s: int, layers: Optional[int] = None) -> SampleResult:
-    circ = sample_circuit(problem, table, s, layers)
+    if getattr(problem, "trotter", False):
+        steps = problem.trotter_steps if layers is None else layers
+        circ = product_formula_circuit(table, steps, s)
+    else:
+        circ = sample_circuit(problem, table, s, layers)
     ops, qubit_at = build_schedule(problem, table, circ, chi_of(problem, s))
     init = getattr(problem, "initial_mps", None)
     mps = (MPS.from_initial(init, problem.svd_cutoff) if init is not None

@@ -23,6 +23,7 @@ PAULI_CODE = {"X": 1, "Y": 2, "Z": 3}
 TEPAI_FP64 = 0
 TEPAI_FP32_MIXED = 1
 TEPAI_NO_PI = 1
+TEPAI_TROTTER = 2
 
 
 class tepai_term(C.Structure):
@@ -185,7 +186,8 @@ class ProblemStruct:
         s.n_strings = len(strings)
         s.strings = C.cast(self._strings, C.POINTER(tepai_pauli_string))
         s.precision = int(precision)
-        s.flags = TEPAI_NO_PI if getattr(p, "no_pi", False) else 0
+        s.flags = ((TEPAI_NO_PI if getattr(p, "no_pi", False) else 0)
+                   | (TEPAI_TROTTER if getattr(p, "trotter", False) else 0))
         init = getattr(p, "initial_mps", None)
         s.initial_mps = None
         if init is not None:

@@ -78,7 +78,15 @@ Table build_table(const tepai_problem& p) {
     HostRow r;
     r.term = k;
     r.theta = theta / (double)m;
-    if (p.flags & TEPAI_NO_PI) {
+    if (p.flags & TEPAI_TROTTER) {
+      // deterministic product formula: the exact rotation every time
+      r.g[0] = 0.0;
+      r.g[1] = 1.0;
+      r.g[2] = 0.0;
+      r.norm1 = 1.0;
+      r.t1 = 0;
+      r.t2 = kThresholdOne;
+    } else if (p.flags & TEPAI_NO_PI) {
       // gamma~ = (1 - lambda, lambda, 0): probabilities themselves, ||.||_1 = 1
       const double lam = std::fabs(r.theta) / p.delta;
       r.g[0] = 1.0 - lam;
@@ -105,7 +113,9 @@ std::vector<DevRow> device_rows(const tepai_problem& p, const Table& t) {
   for (size_t i = 0; i < t.rows.size(); ++i) {
     const HostRow& r = t.rows[i];
     const tepai_term& term = p.terms[r.term];
-    const double phi = r.theta != 0.0 ? std::copysign(p.delta, r.theta) : p.delta;
+    // setting B is R(sign(theta) Delta); under TEPAI_TROTTER it is R(theta)
+    const double phi = (p.flags & TEPAI_TROTTER) ? r.theta
+                       : r.theta != 0.0 ? std::copysign(p.delta, r.theta) : p.delta;
     DevRow d{};
     d.t1 = r.t1;
     d.t2 = r.t2;
@@ -195,7 +205,10 @@ tepai_status validate(tepai_handle* h, const tepai_problem* p) {
   }
   if (p->precision != TEPAI_FP64 && p->precision != TEPAI_FP32_MIXED)
     return fail(h, TEPAI_EINVAL, "unsupported precision");
-  if ((p->flags & ~(uint32_t)TEPAI_NO_PI) != 0) return fail(h, TEPAI_EINVAL, "unsupported flags");
+  if ((p->flags & ~(uint32_t)(TEPAI_NO_PI | TEPAI_TROTTER)) != 0)
+    return fail(h, TEPAI_EINVAL, "unsupported flags");
+  if ((p->flags & TEPAI_NO_PI) && (p->flags & TEPAI_TROTTER))
+    return fail(h, TEPAI_EINVAL, "TEPAI_NO_PI and TEPAI_TROTTER exclude each other");
   return TEPAI_OK;
 }
 

@@ -23,7 +23,8 @@ constexpr double kCutoffMixed = 1e-7;    // mixed path: relative singular-value 
 // One row of the PAI table: a (sub-)rotation of one Trotter step.
 struct DevRow {
   uint64_t t1, t2;      // 63-bit thresholds: v < t1 -> A, v < t2 -> B, else C
-  double cb, sb;        // setting B = cb I - i sb P  (sb = sin(sign(theta) Delta / 2))
+  double cb, sb;        // setting B = cb I - i sb P: sb = sin(sign(theta) Delta / 2), or
+                        // sin(theta / 2) for the deterministic product formula
   uint32_t nq;          // 1 or 2
   uint32_t q0, q1;      // qubits (q1 unused when nq == 1)
   uint32_t p0, p1;      // Pauli codes 1..3

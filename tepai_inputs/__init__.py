@@ -89,6 +89,7 @@ class Problem:
     svd_cutoff: float = 1e-12
     chi_per_sample: Optional[Tuple[int, ...]] = None
     no_pi: bool = False         # biased variant without pi rotations
+    trotter: bool = False       # deterministic product formula: every rotation exact
     initial_mps: Optional[InitialMPS] = None   # start every sample from this state
     name: str = ""
 
@@ -131,6 +132,31 @@ def zz(a: int, b: int) -> Observable:
 
 def half_ring_zz(n: int) -> Observable:
     return tuple(PauliString("ZZ", (i, i + 1)) for i in range(n // 2))
+
+
+def xyz_all(n: int) -> Tuple[Observable, ...]:
+    """Every single-qubit Pauli observable: X_i, Y_i, Z_i for i = 0 .. n-1."""
+    return tuple((PauliString(p, (i,)),) for i in range(n) for p in "XYZ")
+
+
+def product_state(labels: str) -> InitialMPS:
+    """A product state of X or Z eigenstates ('+', '-', '0', '1' per qubit) as
+    a bond-1 MPS, centre on site 0, qubit k on site k."""
+    r = 1.0 / np.sqrt(2.0)
+    vec = {"0": (1.0, 0.0), "1": (0.0, 1.0), "+": (r, r), "-": (r, -r)}
+    tensors = tuple(np.array(vec[c], dtype=np.complex128).reshape(1, 2, 1) for c in labels)
+    return InitialMPS(tensors=tensors, centre=0, qubit_at=tuple(range(len(labels))))
+
+
+def plus_with_minus(n: int) -> str:
+    """|+ ... + - + ... +> with the single '-' on qubit n // 2."""
+    return "+" * (n // 2) + "-" + "+" * (n - n // 2 - 1)
+
+
+def trotter_steps_for(T: float, n_ref: int = 20, dt_ref: float = 0.1) -> int:
+    """N(T) = N_dT (T / dT)^2, the constant-accuracy step count of the
+    first-order reference (eq. trotter-baseline-scaling, N_dT = 20, dT = 0.1)."""
+    return int(round(n_ref * (T / dt_ref) ** 2))
 
 
 # ---------------------------------------------------------------------------
@@ -176,6 +202,25 @@ def config(k: int, **overrides) -> Problem:
                     name="heisenberg_ring_n100_tepai_segment")
     else:
         raise ValueError(f"no configuration {k}")
+    return p.with_(**overrides) if overrides else p
+
+
+def truncation_workload(chi: int, *, trotter: bool = False, n: int = 20, J: float = 1.0,
+                        T: float = 1.0, n_samples: int = 100, seed: int = 7,
+                        **overrides) -> Problem:
+    """The truncation-robustness experiment (sec. "Truncation" and its figure):
+    an n = 20 spin ring (eq. spinRing) with J = 1 and omega_k ~ U[-1, 1], evolved
+    to T = 1 with Delta = pi / 2^12 and N_s = 100 TE-PAI circuits, or with the
+    deterministic product formula (``trotter``), at bond cap ``chi``; the
+    start is |+ ... + - + ... +> and the observables are X, Y and Z of every
+    qubit.  N = N(T) of the first-order reference rule."""
+    fields = disorder(n, -1.0, 1.0, seed=seed)
+    p = Problem(n_qubits=n, terms=spin_ring(n, fields, j_xy=J, j_z=J), total_time=T,
+                trotter_steps=trotter_steps_for(T), delta=np.pi / 2 ** 12,
+                n_samples=1 if trotter else n_samples, seed=seed, chi_max=chi,
+                initial_bits="0" * n, observables=xyz_all(n), trotter=trotter,
+                initial_mps=product_state(plus_with_minus(n)),
+                name=f"ring_n{n}_J{J:g}_T{T:g}_{'trotter' if trotter else 'tepai'}_chi{chi}")
     return p.with_(**overrides) if overrides else p
 
 

@@ -91,6 +91,26 @@ def test_host_table_equals_oracle_table(k, no_pi):
         assert t["log_g1_step"] == 0.0 and np.all(t["thresholds"][:, 1] == 2 ** 63)
 
 
+@pytest.mark.parametrize("k", [1, 4])
+def test_host_table_trotter_equals_oracle_table(k):
+    p = ti.config(k).with_(trotter=True)
+    t = L.tepai_pai_table(None, L.ProblemStruct(p))
+    o = pai.build_table(p)
+    assert np.array_equal(t["theta"], [r.theta for r in o.rows])
+    assert np.array_equal(t["gamma"], np.array([r.gamma for r in o.rows]))
+    thr = np.array([[r.t1, r.t2] for r in o.rows], dtype=np.uint64)
+    assert np.array_equal(t["thresholds"], thr)
+    assert np.all(t["thresholds"][:, 0] == 0) and np.all(t["thresholds"][:, 1] == 2 ** 63)
+    assert t["log_g1_step"] == 0.0 == o.log_g1_step
+
+
+def test_trotter_and_no_pi_exclude_each_other():
+    L.tepai_validate(None, L.ProblemStruct(ti.config(1).with_(trotter=True)))
+    with pytest.raises(L.TepaiError) as e:
+        L.tepai_validate(None, L.ProblemStruct(ti.config(1).with_(trotter=True, no_pi=True)))
+    assert e.value.status == -1
+
+
 def bad(**kw):
     return ti.config(1).with_(**kw)
 

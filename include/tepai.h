@@ -240,6 +240,22 @@ tepai_status tepai_batch_observe(tepai_batch* b, double* d_values, double* d_wei
 /* Copy the per-sample counters to the host ([count] records); synchronises
  * the batch's stream. */
 tepai_status tepai_batch_stats(tepai_batch* b, tepai_sample_stats* stats);
+/* Copy the MPS of batch slot `slot` (sample sample_offset+first+slot) at its
+ * current step to the host, in the form of tepai_mps, so that a state the
+ * GPU evolved can start other samples (hybrid start: a TEPAI_TROTTER batch
+ * evolved to t0, then TE-PAI from its state; sec. "Implementation",
+ * Trotter-then-TE-PAI).  Writes bond[n_qubits + 1], qubit_at[n_qubits],
+ * *centre and *n_values = sum_k 2 bond[k] bond[k+1] (complex values); then,
+ * if `tensors` is not NULL and n_values <= capacity (complex values), the
+ * site tensors as interleaved (re, im) doubles, site after site, each
+ * A_k[a][s][c] row-major (complex64 tensors of the mixed path are widened).
+ * Sites left of the centre are left-canonical, right of it right-canonical,
+ * and the state has unit norm.  Synchronises the batch's stream.  Returns
+ * TEPAI_ERANGE for slot >= count and TEPAI_ENOMEM (outputs other than
+ * `tensors` written) when capacity is too small.  Host pointers. */
+tepai_status tepai_batch_read_mps(tepai_batch* b, uint32_t slot, uint64_t capacity,
+                                  uint32_t* bond, uint32_t* qubit_at, uint32_t* centre,
+                                  uint64_t* n_values, double* tensors);
 void tepai_batch_destroy(tepai_batch* b);
 
 /* Weighted reduction on the device (Statement 2): x_s = w_s v_s,

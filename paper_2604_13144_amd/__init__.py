@@ -6,10 +6,10 @@ the C names.  PyTorch only provides device memory and streams.
 """
 from ._lib import (Batch, Handle, ProblemStruct, TepaiError, load, tepai_batch_create,
                    tepai_batch_destroy, tepai_batch_evolve, tepai_batch_observe,
-                   tepai_batch_stats, tepai_pai_table, tepai_reduce, tepai_run,
+                   tepai_batch_read_mps, tepai_batch_stats, tepai_pai_table, tepai_reduce, tepai_run,
                    tepai_sample_circuits, tepai_validate, tepai_workspace_size)
 
 __all__ = ["Batch", "Handle", "ProblemStruct", "TepaiError", "load", "tepai_batch_create",
            "tepai_batch_destroy", "tepai_batch_evolve", "tepai_batch_observe",
-           "tepai_batch_stats", "tepai_pai_table", "tepai_reduce", "tepai_run",
+           "tepai_batch_read_mps", "tepai_batch_stats", "tepai_pai_table", "tepai_reduce", "tepai_run",
            "tepai_sample_circuits", "tepai_validate", "tepai_workspace_size"]

@@ -89,6 +89,8 @@ PROTOTYPES = {
     "tepai_batch_evolve": (C.c_int, [_P, C.c_uint32]),
     "tepai_batch_observe": (C.c_int, [_P, _P, _P]),
     "tepai_batch_stats": (C.c_int, [_P, C.POINTER(tepai_sample_stats)]),
+    "tepai_batch_read_mps": (C.c_int, [_P, C.c_uint32, C.c_uint64, _P, _P,
+                                       C.POINTER(C.c_uint32), C.POINTER(C.c_uint64), _P]),
     "tepai_batch_destroy": (None, [_P]),
     "tepai_reduce": (C.c_int, [_P, C.c_uint64, C.c_uint32, _P, _P, _P, _P, _P]),
     "tepai_run": (C.c_int, [_P, C.POINTER(tepai_problem), C.c_uint32, _P, _P, _P, _P,
@@ -286,6 +288,16 @@ def tepai_workspace_size(h: Optional[Handle], ps: ProblemStruct, count: int) -> 
     return b.value
 
 
+class MPSState:
+    """A host copy of one sample's MPS, in the form a problem's initial_mps takes."""
+
+    def __init__(self, tensors, centre, qubit_at):
+        self.tensors, self.centre, self.qubit_at = tensors, centre, qubit_at
+
+    def bonds(self):
+        return (1,) + tuple(int(a.shape[2]) for a in self.tensors)
+
+
 class Batch:
     """A batch of samples living in a torch-allocated device workspace."""
 
@@ -323,6 +335,27 @@ class Batch:
                 out[f][i] = getattr(arr[i], f)
         return out
 
+    def read_mps(self, slot: int) -> "MPSState":
+        """The MPS of one slot at its current step (host copy, complex128)."""
+        n = int(self.ps.struct.n_qubits)
+        bond = np.zeros(n + 1, dtype=np.uint32)
+        qubit_at = np.zeros(n, dtype=np.uint32)
+        centre, total = C.c_uint32(), C.c_uint64()
+        lib = load()
+        _check(lib.tepai_batch_read_mps(self.b, slot, 0, bond.ctypes.data, qubit_at.ctypes.data,
+                                        C.byref(centre), C.byref(total), None), self.h.h)
+        buf = np.zeros(2 * total.value, dtype=np.float64)
+        _check(lib.tepai_batch_read_mps(self.b, slot, total.value, bond.ctypes.data,
+                                        qubit_at.ctypes.data, C.byref(centre), C.byref(total),
+                                        buf.ctypes.data), self.h.h)
+        vals = buf.view(np.complex128)
+        tensors, at = [], 0
+        for k in range(n):
+            a, c = int(bond[k]), int(bond[k + 1])
+            tensors.append(vals[at:at + 2 * a * c].reshape(a, 2, c).copy())
+            at += 2 * a * c
+        return MPSState(tuple(tensors), int(centre.value), tuple(int(q) for q in qubit_at))
+
     def close(self):
         if self.b:
             load().tepai_batch_destroy(self.b)
@@ -349,6 +382,10 @@ def tepai_batch_observe(b: Batch, d_values, d_weights) -> None:
 
 def tepai_batch_stats(b: Batch) -> np.ndarray:
     return b.stats()
+
+
+def tepai_batch_read_mps(b: Batch, slot: int) -> MPSState:
+    return b.read_mps(slot)
 
 
 def tepai_batch_destroy(b: Batch) -> None:

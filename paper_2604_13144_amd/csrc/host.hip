@@ -565,6 +565,47 @@ tepai_status tepai_batch_stats(tepai_batch* b, tepai_sample_stats* out) {
   return TEPAI_OK;
 }
 
+tepai_status tepai_batch_read_mps(tepai_batch* b, uint32_t slot, uint64_t capacity,
+                                  uint32_t* bond, uint32_t* qubit_at, uint32_t* centre,
+                                  uint64_t* n_values, double* tensors) {
+  if (!b || !bond || !qubit_at || !centre || !n_values) return TEPAI_EINVAL;
+  if (slot >= b->args.count) return fail(b->h, TEPAI_ERANGE, "slot out of range");
+  TEPAI_HIP(b->h, hipSetDevice(b->h->device));
+  SampleState st;
+  TEPAI_HIP(b->h, hipMemcpyAsync(&st, b->args.states + slot, sizeof(SampleState), hipMemcpyDeviceToHost, b->stream));
+  TEPAI_HIP(b->h, hipStreamSynchronize(b->stream));
+  const uint32_t n = b->args.n;
+  uint64_t total = 0;
+  for (uint32_t k = 0; k <= n; ++k) bond[k] = st.bond[k];
+  for (uint32_t k = 0; k < n; ++k) {
+    qubit_at[k] = st.qubit_at[k];
+    total += 2ull * st.bond[k] * st.bond[k + 1];
+  }
+  *centre = (uint32_t)st.centre;
+  *n_values = total;
+  if (!tensors) return TEPAI_OK;
+  if (total > capacity) return fail(b->h, TEPAI_ENOMEM, "tensor capacity too small");
+  // each site's tensor is the first 2 bond[k] bond[k+1] values of its slot
+  const bool mixed = b->args.mixed != 0;
+  const size_t elem = mixed ? sizeof(float2) : sizeof(double2);
+  const char* base = reinterpret_cast<const char*>(b->args.tensors);
+  std::vector<float2> narrow(mixed ? total : 0);
+  uint64_t at = 0;
+  for (uint32_t k = 0; k < n; ++k) {
+    const uint64_t m = 2ull * st.bond[k] * st.bond[k + 1];
+    const char* src = base + ((uint64_t)slot * n + k) * b->args.site_stride * elem;
+    void* dst = mixed ? (void*)(narrow.data() + at) : (void*)(tensors + 2 * at);
+    TEPAI_HIP(b->h, hipMemcpyAsync(dst, src, m * elem, hipMemcpyDeviceToHost, b->stream));
+    at += m;
+  }
+  TEPAI_HIP(b->h, hipStreamSynchronize(b->stream));
+  for (uint64_t i = 0; i < narrow.size(); ++i) {
+    tensors[2 * i] = narrow[i].x;
+    tensors[2 * i + 1] = narrow[i].y;
+  }
+  return TEPAI_OK;
+}
+
 void tepai_batch_destroy(tepai_batch* b) { delete b; }
 
 tepai_status tepai_reduce(tepai_handle* h, uint64_t count, uint32_t n_obs, const double* d_values,

@@ -45,3 +45,67 @@ def test_hybrid_mixed(handle):
     print("hybrid mixed: ring n=12 chi=10", flush=True)
     vals, _, st = run_batch(handle, p, p.n_samples, [6], L.TEPAI_FP32_MIXED)
     print("hybrid mixed worst", against_oracle(p, vals, st))
+
+
+# --- the whole hybrid on the GPU: TEPAI_TROTTER batch to t0, read its MPS,
+# --- start the TE-PAI samples from it (the oracle prepares its own start)
+
+def canonical_ok(m, tol):
+    for k, A in enumerate(m.tensors):
+        cl, _, cr = A.shape
+        if k < m.centre:
+            M = A.reshape(cl * 2, cr)
+            assert np.allclose(M.conj().T @ M, np.eye(cr), atol=tol)
+        elif k > m.centre:
+            M = A.reshape(cl, 2 * cr)
+            assert np.allclose(M @ M.conj().T, np.eye(cl), atol=tol)
+
+
+def gpu_trotter_state(handle, pre, steps, precision=L.TEPAI_FP64):
+    b = L.Batch(handle, L.ProblemStruct(pre.with_(trotter=True, n_samples=1), precision=precision), 0, 1)
+    b.evolve(steps)
+    m = b.read_mps(0)
+    b.close()
+    return m
+
+
+def test_read_mps_initial_product_state(handle):
+    p = ti.small_ring(6, seed=1, n_samples=2)
+    b = L.Batch(handle, L.ProblemStruct(p), 0, 2)
+    m = b.read_mps(1)
+    assert m.bonds() == (1,) * 7 and m.qubit_at == tuple(range(6)) and m.centre == 0
+    for k, A in enumerate(m.tensors):
+        e = np.zeros((1, 2, 1), complex)
+        e[0, int(p.initial_bits[k]), 0] = 1.0
+        assert np.array_equal(A, e)
+    with pytest.raises(L.TepaiError) as err:
+        b.read_mps(2)
+    assert err.value.status == -2
+
+
+@pytest.mark.parametrize("precision,tol", [(L.TEPAI_FP64, 1e-10), (L.TEPAI_FP32_MIXED, 1e-5)])
+def test_read_mps_of_gpu_trotter_equals_oracle_state(handle, precision, tol):
+    from test_oracle_hybrid import dense_of
+    pre = ti.small_ring(12, seed=9, T=0.8, N=10, delta=math.pi / 16, chi=10, n_samples=1)
+    print(f"read_mps: GPU Trotter n=12 chi=10, 10 steps, precision {precision}", flush=True)
+    m = gpu_trotter_state(handle, pre, 10, precision)
+    ref = trotter_initial_mps(pre, 10, 10)
+    assert m.qubit_at == ref.qubit_at and m.centre == ref.centre
+    if precision == L.TEPAI_FP64:
+        assert m.bonds() == ref.bonds() and max(m.bonds()) == 10
+    else:       # the mixed path's 1e-7 singular-value floor may keep fewer
+        assert all(a <= b for a, b in zip(m.bonds(), ref.bonds()))
+    canonical_ok(m, 1e-12 if precision == L.TEPAI_FP64 else 1e-5)
+    a, r = dense_of(m), dense_of(ref)
+    assert abs(np.linalg.norm(a) - 1.0) < tol
+    assert 1.0 - abs(np.vdot(r, a)) < tol
+
+
+def test_gpu_only_hybrid_matches_oracle_hybrid(handle):
+    pre = ti.small_ring(12, seed=9, T=0.8, N=10, delta=math.pi / 16, chi=10, n_samples=1)
+    print("hybrid on the GPU: Trotter to t0, read_mps, TE-PAI segment", flush=True)
+    m = gpu_trotter_state(handle, pre, 10)
+    seg = pre.with_(total_time=0.3, trotter_steps=6, n_samples=5)
+    vals, wts, st = gpu_batch(handle, seg.with_(initial_mps=m), 0, 5, [6])
+    # the oracle runs the same segment from its own Trotter state
+    compare(seg.with_(initial_mps=trotter_initial_mps(pre, 10, 10)), range(5), vals, wts, st, 0)

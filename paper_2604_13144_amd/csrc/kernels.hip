@@ -619,9 +619,9 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_, do
         }
         __syncthreads();
       }
-      // pairs inside block I, in LDS (round-robin over the JB columns); each
-      // of the JB/2 pairs of a round is shared by G rows of one wave, so
-      // every row of the workgroup works
+      // pairs inside block I, in LDS (round-robin over the block's columns,
+      // rounded up to an even count); each of the pairs of a round is shared
+      // by G rows of one wave, so every row of the workgroup works
       if (row < JB) {
         row_store_l<E>(xi, Jl + row * LR, l16);
         if (l16 == 0) jn[row] = al;
@@ -630,11 +630,14 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_, do
       {
         constexpr int G = NROWS / (JB / 2), EG = E / G;
         const int k = row / G, h = row - k * G;
+        const int ncol = (C - I * JB) < JB ? (C - I * JB) : JB;
+        const int Cp = ncol + (ncol & 1);
 #pragma unroll 1
-        for (int round = 0; round < JB - 1; ++round) {
-          int p, q;
-          rr_pair(round, k, JB, p, q);
-          const bool act = I * JB + q < C;
+        for (int round = 0; round < Cp - 1; ++round) {
+          int p = 0, q = 1;
+          const bool pk = k < Cp / 2;
+          if (pk) rr_pair(round, k, Cp, p, q);
+          const bool act = pk && I * JB + q < C;
           tmx = fmax(tmx, rotate_split<EG, G>(Jl + p * LR, Jl + q * LR, jn + p, jn + q, h * EG,
                                                l16, h == 0, act, tiny, tol2));
           __syncthreads();

@@ -68,3 +68,15 @@ def test_truncation_workload_prefix(handle, chi, trotter):
     vals, wts, st = gpu_batch(handle, p, 0, p.n_samples, [10, 20])
     assert max(st["max_bond"]) <= chi
     compare(p, range(p.n_samples), vals, wts, st, 0, layers=30)
+
+
+def test_truncation_workload_full_length_chi2(handle):
+    # all 2000 steps of the experiment at chi = 2 (77.9k truncated updates per
+    # circuit): the product formula and two TE-PAI circuits against the oracle
+    # (a sample with a tie at a cut is checked for its counts and flag only)
+    for trotter, ns in ((True, 1), (False, 2)):
+        p = ti.truncation_workload(2, trotter=trotter).with_(n_samples=ns)
+        print(f"truncation workload full length: trotter={trotter} chi=2", flush=True)
+        vals, wts, st = gpu_batch(handle, p, 0, ns, [p.trotter_steps])
+        assert int(st["updates"][0]) > 70_000
+        compare(p, range(ns), vals, wts, st, 0)

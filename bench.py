@@ -64,7 +64,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=12)
-    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--batch", type=int, default=None,
+                    help="samples resident at once (default 256, one per CU; the hybrid "
+                         "workload 768, so that CUs done with a small-cap sample take another)")
     ap.add_argument("--layers-per-step", type=int, default=8)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -72,9 +74,15 @@ def parse():
                     help="comma list of paths to time (the first one gives value)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (counter calibration) and exit")
-    ap.add_argument("--workload", choices=("throughput", "truncation"), default="throughput",
-                    help="truncation: the chi = 2 vs 16 robustness experiment instead of "
-                         "the throughput step")
+    ap.add_argument("--workload", choices=("throughput", "truncation", "hybrid"),
+                    default="throughput",
+                    help="truncation: the chi = 2 vs 16 robustness experiment; hybrid: "
+                         "Trotter-then-TE-PAI on the n = 100 ring (use --layers-per-step 32 "
+                         "--warmup 4); default: the throughput step")
+    ap.add_argument("--t0", type=float, default=0.5,
+                    help="hybrid workload: length of the Trotter segment")
+    ap.add_argument("--no-pi", action="store_true",
+                    help="hybrid workload: the biased variant without pi rotations")
     ap.add_argument("--read-every", type=int, default=100,
                     help="truncation workload: Trotter steps between read-outs")
     ap.add_argument("--delta-log2", type=int, default=12,
@@ -102,17 +110,18 @@ def workload(batch):
 
 # ----------------------------------------------------------- CPU baseline
 def _oracle_worker(args):
-    sample, seconds = args
+    sample, seconds, kind = args
     os.environ["OMP_NUM_THREADS"] = "1"
     import numpy as np  # noqa: F401
     from oracle import pai
     from oracle.mps import MPS
     from oracle.sampler import sample_circuit
     from oracle.schedule import build_schedule
-    p = workload(1)
+    p = workload(1) if kind == "throughput" else hybrid_segment(16, False)
     t = pai.build_table(p)
     circ = sample_circuit(p, t, sample)
-    ops, _ = build_schedule(p, t, circ, p.chi_max)
+    chi = p.chi_max if p.chi_per_sample is None else p.chi_per_sample[sample]
+    ops, _ = build_schedule(p, t, circ, chi)
     L = t.l_eff
     # layer boundaries in the op list: count ops until the time budget ends
     m = MPS(p.initial_bits, p.svd_cutoff)
@@ -128,11 +137,11 @@ def _oracle_worker(args):
     return frac_updates, el, m.stats.updates, max(m.bonds())
 
 
-def cpu_baseline(seconds: float):
+def cpu_baseline(seconds: float, kind: str = "throughput"):
     cores = min(os.cpu_count() or 1, 16)
     ctx = mp.get_context("spawn")
     with ctx.Pool(cores) as pool:
-        res = pool.map(_oracle_worker, [(s, seconds) for s in range(cores)])
+        res = pool.map(_oracle_worker, [(s, seconds, kind) for s in range(cores)])
     frac = sum(r[0] for r in res)
     wall = max(r[1] for r in res)
     return {"value": frac / wall, "unit": "samples/s", "cores": cores, "kind": "oracle",
@@ -298,6 +307,122 @@ def truncation_experiment(L, h, read_every, delta_log2=12):
     }
 
 
+def hybrid_segment(n_samples, no_pi, initial_mps=None):
+    """The TE-PAI segment of the combined long-time configuration: the n = 100
+    Heisenberg ring (h ~ U[-1,1]), T = 2, N = 1024, Delta = pi/512, bond caps
+    16, 32, 64 in turn over the samples, <Z_i> and the half-ring sum of
+    Z_i Z_{i+1}."""
+    import tepai_inputs as ti
+    caps = tuple((16, 32, 64)[s % 3] for s in range(n_samples))
+    return ti.config(5).with_(n_samples=n_samples, chi_per_sample=caps, no_pi=no_pi,
+                              initial_mps=initial_mps)
+
+
+def hybrid_experiment(L, h, a):
+    """Trotter-then-TE-PAI on the GPU (sec. "Implementation"): a deterministic
+    product-formula segment of one sample to t0 (TEPAI_TROTTER, bond cap 16,
+    N(t0) steps of the first-order reference rule), its MPS read back, then
+    a batch of TE-PAI samples (or the biased no-pi variant) continuing from
+    that shared state with per-sample caps 16/32/64.  W windows of J steps
+    warm the batch up, K windows are timed; every window ends with a
+    read-out and the weighted reduction (time series of the estimate)."""
+    import numpy as np
+    import torch
+    import tepai_inputs as ti
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    t0_time = a.t0
+    n0 = ti.trotter_steps_for(t0_time)
+    pre = ti.config(5).with_(trotter=True, total_time=t0_time, trotter_steps=n0,
+                             n_samples=1, chi_max=16)
+    bt = L.Batch(h, L.ProblemStruct(pre), 0, 1, stream=stream)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    step = max(1, n0 // 10)
+    for j in range(0, n0, step):
+        bt.evolve(min(step, n0 - j))
+        torch.cuda.synchronize()
+        print(f"[bench] hybrid Trotter segment: step {min(j + step, n0)}/{n0}", file=sys.stderr, flush=True)
+    prep_s = time.perf_counter() - tp
+    shared = bt.read_mps(0)
+    prep_stats = bt.stats()
+    bt.close()
+    B, J, K, W = a.batch or 768, a.layers_per_step, a.steps, a.warmup
+    p = hybrid_segment(B, a.no_pi, shared)
+    if (W + K) * J > p.trotter_steps:
+        raise SystemExit("warmup + steps exceed the circuit")
+    ps = L.ProblemStruct(p)
+    b = L.Batch(h, ps, 0, B, stream=stream)
+    n_obs = ps.n_obs
+    vals = torch.empty(B * n_obs, dtype=torch.float64, device=dev)
+    wts = torch.empty(B, dtype=torch.float64, device=dev)
+    mean = torch.empty(n_obs, dtype=torch.float64, device=dev)
+    se = torch.empty(n_obs, dtype=torch.float64, device=dev)
+    series = []
+    s0 = None
+    evolve_ms, t_timed = 0.0, 0.0
+    for i in range(W + K):
+        timed = i >= W
+        if timed and s0 is None:
+            torch.cuda.synchronize()
+            s0 = b.stats()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        tw = time.perf_counter()
+        e0.record(stream)
+        b.evolve(J)
+        e1.record(stream)
+        b.observe(vals, wts)
+        L.tepai_reduce(h, B, n_obs, vals, wts, mean, se, stream)
+        torch.cuda.synchronize()
+        if timed:
+            t_timed += time.perf_counter() - tw
+            evolve_ms += e0.elapsed_time(e1)
+        m, e = mean.cpu().numpy(), se.cpu().numpy()
+        t_now = t0_time + (i + 1) * J * p.total_time / p.trotter_steps
+        series.append([round(t_now, 6), float(m[0]), float(e[0]), float(m[-1]), float(e[-1])])
+        print(f"[bench] hybrid TE-PAI window {i + 1}/{W + K}{' (timed)' if timed else ''}: "
+              f"{time.perf_counter() - tw:.1f} s", file=sys.stderr, flush=True)
+    s1 = b.stats()
+    b.close()
+    d = {f: float(np.sum(s1[f].astype(np.float64) - s0[f].astype(np.float64)))
+         for f in ("n_gates", "updates", "nominal_flops")}
+    achieved = d["nominal_flops"] / (evolve_ms / 1e3) / 1e12
+    line = {
+        "metric": "TE-PAI MPS samples/s from a shared Trotter state (hybrid), n=100 ring, chi 16/32/64",
+        "value": B * K * J / p.trotter_steps / t_timed,
+        "unit": "samples/s",
+        "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": t_timed / K * 1e3,
+        "higher_is_better": True,
+        "dtype": "f64",
+        "data": "synthetic",
+        "variant": "no_pi (biased, Statement 3)" if a.no_pi else "unbiased TE-PAI",
+        "config": {"workload": "hybrid: n=100 Heisenberg ring h~U[-1,1]; Trotter segment to "
+                               f"t0={t0_time:g} (N0={n0}, chi=16) on the GPU, then TE-PAI T=2, "
+                               "N=1024, Delta=pi/512, caps 16/32/64, Neel start of the segment",
+                   "batch_samples": B, "trotter_steps_per_step": J,
+                   "timed_trotter_steps": [W * J, (W + K) * J]},
+        "trotter_segment": {"seconds": prep_s, "steps": n0, "updates": int(prep_stats["updates"][0]),
+                            "max_bond": int(prep_stats["max_bond"][0]),
+                            "shared_state_bonds_max": max(shared.bonds())},
+        "gates_per_s": d["n_gates"] / t_timed,
+        "updates_per_s": d["updates"] / t_timed,
+        "series_t_Z0_se_halfZZ_se": series,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "evolve_kernel<2, false> (FP64)",
+                     "kernel_ms_per_launch": evolve_ms / K,
+                     "flops_per_launch": d["nominal_flops"] / K},
+    }
+    if not a.no_cpu_baseline:
+        cb = cpu_baseline(a.cpu_seconds, "hybrid")
+        cb["sample"] = cb["sample"].replace("the same workload", "the TE-PAI segment").replace(
+            "from t=0", "from the Neel product state (the oracle does not take the GPU's shared state)")
+        line["cpu_baseline"] = cb
+    return line
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -305,6 +430,12 @@ def main():
         sys.exit(2)
     if a.copy_probe:
         copy_probe(a.copy_probe)
+        return
+    if a.workload == "hybrid":
+        import torch
+        torch.cuda.init()
+        from paper_2604_13144_amd import _lib as L
+        print(json.dumps(hybrid_experiment(L, L.Handle(0), a)))
         return
     if a.workload == "truncation":
         import torch
@@ -317,8 +448,9 @@ def main():
     torch.cuda.init()          # torch's HIP context first, then the library's handle
     from paper_2604_13144_amd import _lib as L
 
-    p = workload(a.batch)
-    J, K, W, B = a.layers_per_step, a.steps, a.warmup, a.batch
+    B = a.batch or 256
+    p = workload(B)
+    J, K, W = a.layers_per_step, a.steps, a.warmup
     if (W + K) * J > p.trotter_steps:
         raise SystemExit("warmup + steps exceed the circuit")
     h = L.Handle(0)

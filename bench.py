@@ -83,6 +83,8 @@ def parse():
                     help="hybrid workload: length of the Trotter segment")
     ap.add_argument("--no-pi", action="store_true",
                     help="hybrid workload: the biased variant without pi rotations")
+    ap.add_argument("--cycle-caps", action="store_true",
+                    help="hybrid workload: caps 16, 32, 64 in turn instead of largest first")
     ap.add_argument("--read-every", type=int, default=100,
                     help="truncation workload: Trotter steps between read-outs")
     ap.add_argument("--delta-log2", type=int, default=12,
@@ -307,13 +309,18 @@ def truncation_experiment(L, h, read_every, delta_log2=12):
     }
 
 
-def hybrid_segment(n_samples, no_pi, initial_mps=None):
+def hybrid_segment(n_samples, no_pi, initial_mps=None, cycled=False):
     """The TE-PAI segment of the combined long-time configuration: the n = 100
     Heisenberg ring (h ~ U[-1,1]), T = 2, N = 1024, Delta = pi/512, bond caps
-    16, 32, 64 in turn over the samples, <Z_i> and the half-ring sum of
-    Z_i Z_{i+1}."""
+    64, 32 and 16 for the first, second and last third of the samples, <Z_i>
+    and the half-ring sum of Z_i Z_{i+1}.  Workgroups start in sample order,
+    so the largest caps (the longest work) start first and the small-cap
+    samples fill the CUs that free up."""
     import tepai_inputs as ti
-    caps = tuple((16, 32, 64)[s % 3] for s in range(n_samples))
+    if cycled:      # 16, 32, 64 in turn (for comparison)
+        caps = tuple((16, 32, 64)[s % 3] for s in range(n_samples))
+    else:
+        caps = tuple((64, 32, 16)[min(2, 3 * s // n_samples)] for s in range(n_samples))
     return ti.config(5).with_(n_samples=n_samples, chi_per_sample=caps, no_pi=no_pi,
                               initial_mps=initial_mps)
 
@@ -348,7 +355,7 @@ def hybrid_experiment(L, h, a):
     prep_stats = bt.stats()
     bt.close()
     B, J, K, W = a.batch or 768, a.layers_per_step, a.steps, a.warmup
-    p = hybrid_segment(B, a.no_pi, shared)
+    p = hybrid_segment(B, a.no_pi, shared, a.cycle_caps)
     if (W + K) * J > p.trotter_steps:
         raise SystemExit("warmup + steps exceed the circuit")
     ps = L.ProblemStruct(p)
@@ -389,7 +396,7 @@ def hybrid_experiment(L, h, a):
          for f in ("n_gates", "updates", "nominal_flops")}
     achieved = d["nominal_flops"] / (evolve_ms / 1e3) / 1e12
     line = {
-        "metric": "TE-PAI MPS samples/s from a shared Trotter state (hybrid), n=100 ring, chi 16/32/64",
+        "metric": "TE-PAI MPS samples/s from a shared Trotter state (hybrid), n=100 ring, chi 64/32/16",
         "value": B * K * J / p.trotter_steps / t_timed,
         "unit": "samples/s",
         "n_gpus": 1, "steps": K, "warmup": W,
@@ -400,7 +407,7 @@ def hybrid_experiment(L, h, a):
         "variant": "no_pi (biased, Statement 3)" if a.no_pi else "unbiased TE-PAI",
         "config": {"workload": "hybrid: n=100 Heisenberg ring h~U[-1,1]; Trotter segment to "
                                f"t0={t0_time:g} (N0={n0}, chi=16) on the GPU, then TE-PAI T=2, "
-                               "N=1024, Delta=pi/512, caps 16/32/64, Neel start of the segment",
+                               "N=1024, Delta=pi/512, caps " + ("16/32/64 in turn" if a.cycle_caps else "64/32/16 by thirds") + ", Neel start of the segment",
                    "batch_samples": B, "trotter_steps_per_step": J,
                    "timed_trotter_steps": [W * J, (W + K) * J]},
         "trotter_segment": {"seconds": prep_s, "steps": n0, "updates": int(prep_stats["updates"][0]),

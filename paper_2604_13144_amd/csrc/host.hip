@@ -241,8 +241,8 @@ Layout layout(const tepai_problem& p, uint32_t l_eff, uint32_t count) {
   off = align256(off + sizeof(DevString) * std::max<uint32_t>(p.n_strings, 1));
   L.bits = off;
   off = align256(off + p.n_qubits);
-  L.caps = off;
-  off = align256(off + sizeof(uint32_t) * count);
+  L.caps = off;     // per-slot caps, then the launch order of the slots
+  off = align256(off + sizeof(uint32_t) * 2 * count);
   L.states = off;
   off = align256(off + sizeof(SampleState) * count);
   L.tensors = off;
@@ -434,15 +434,25 @@ tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_
     b->bits.assign(p->initial_bits, p->initial_bits + p->n_qubits);
   else
     b->bits.assign(p->n_qubits, 0);
-  b->caps.resize(count);
+  b->caps.resize(2 * (size_t)count);
   for (uint32_t i = 0; i < count; ++i)
     b->caps[i] = p->chi_per_sample ? p->chi_per_sample[first + i] : p->chi_max;
+  // workgroups start roughly in index order and a CU runs one sample at a
+  // time, so the slots are launched by decreasing bond cap (stable): the
+  // longest samples start first and the cheap ones fill the CUs that free up
+  {
+    uint32_t* ord = b->caps.data() + count;
+    for (uint32_t i = 0; i < count; ++i) ord[i] = i;
+    const uint32_t* cap = b->caps.data();
+    std::stable_sort(ord, ord + count, [cap](uint32_t x, uint32_t y) { return cap[x] > cap[y]; });
+  }
   char* ws = (char*)workspace;
   EngineArgs& a = b->args;
   a.rows = (const DevRow*)(ws + lay.rows);
   a.strings = (const DevString*)(ws + lay.strings);
   a.init_bits = (const uint8_t*)(ws + lay.bits);
   a.chi_caps = (const uint32_t*)(ws + lay.caps);
+  a.launch_order = a.chi_caps + count;
   a.states = (SampleState*)(ws + lay.states);
   a.tensors = (double2*)(ws + lay.tensors);
   a.work = (double2*)(ws + lay.work);
@@ -498,7 +508,7 @@ tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_
   if (e == hipSuccess)
     e = hipMemcpyAsync(ws + lay.bits, b->bits.data(), p->n_qubits, hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(ws + lay.caps, b->caps.data(), sizeof(uint32_t) * count, hipMemcpyHostToDevice, b->stream);
+    e = hipMemcpyAsync(ws + lay.caps, b->caps.data(), sizeof(uint32_t) * 2 * count, hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess && a.init_tensors) {
     e = hipMemcpyAsync((void*)a.init_off, b->init_off.data(), sizeof(uint64_t) * (n + 1), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)

@@ -1705,7 +1705,7 @@ template <int RPL, bool MIX>
 __global__ __launch_bounds__(NT) void evolve_kernel(EngineArgs a, uint32_t n_layers) {
   __shared__ Shared sh;
   __shared__ z2 Jl[jl_size<RPL>()];
-  const int slot = blockIdx.x;
+  const int slot = (int)a.launch_order[blockIdx.x];
   const Slot S = make_slot<MIX>(a, slot, Jl);
   load_state(a, slot, sh);
   const uint32_t sample = (uint32_t)(a.first_sample + slot);

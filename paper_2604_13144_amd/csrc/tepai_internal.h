@@ -58,6 +58,7 @@ struct EngineArgs {
   const DevString* strings;
   const uint8_t* init_bits;
   const uint32_t* chi_caps;   // [count] per-slot bond caps
+  const uint32_t* launch_order;  // [count] slot run by workgroup b (decreasing cap)
   SampleState* states;
   double2* tensors;       // [count][n][site_stride]
   double2* work;          // [count][work_stride]

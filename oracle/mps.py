@@ -165,6 +165,8 @@ class MPS:
         for k, A in enumerate(self.A):
             O = ops_at_site[k]
             AO = A if O is None else np.einsum("st,atb->asb", O, A)
-            E = np.einsum("xy,xsa,ysb->ab", E, A.conj(), AO)
-            N = np.einsum("xy,xsa,ysb->ab", N, A.conj(), A)
+            # the same triple sum, contracted pairwise (E with A^*, then with
+            # AO) so that it costs chi^3 per site instead of chi^4
+            E = np.einsum("xy,xsa,ysb->ab", E, A.conj(), AO, optimize=True)
+            N = np.einsum("xy,xsa,ysb->ab", N, A.conj(), A, optimize=True)
         return complex(E[0, 0] / N[0, 0])

@@ -148,6 +148,27 @@ def product_state(labels: str) -> InitialMPS:
     return InitialMPS(tensors=tensors, centre=0, qubit_at=tuple(range(len(labels))))
 
 
+def random_mps(n: int, chi: int, seed: int) -> InitialMPS:
+    """A seeded random state with every bond at min(2^k, 2^(n-k), chi).
+
+    Site tensors have i.i.d. complex Gaussian entries; sweeping from the last
+    site to the first, each is replaced by the row-orthonormal factor of its
+    (chi_k, 2 chi_{k+1}) matrix and the triangular rest is pushed into its
+    left neighbour, so every site right of site 0 is right-canonical and the
+    norm sits in site 0, which is scaled to 1.  Qubit k is on site k.
+    """
+    rng = np.random.default_rng(seed)
+    bonds = [min(2 ** k, 2 ** (n - k), chi) for k in range(n + 1)]
+    ts = [rng.standard_normal((bonds[k], 2, bonds[k + 1]))
+          + 1j * rng.standard_normal((bonds[k], 2, bonds[k + 1])) for k in range(n)]
+    for k in range(n - 1, 0, -1):
+        q, r = np.linalg.qr(ts[k].reshape(bonds[k], -1).conj().T)
+        ts[k] = q.conj().T.reshape(bonds[k], 2, bonds[k + 1])
+        ts[k - 1] = np.tensordot(ts[k - 1], r.conj().T, axes=(2, 0))
+    ts[0] = ts[0] / np.linalg.norm(ts[0])
+    return InitialMPS(tensors=tuple(ts), centre=0, qubit_at=tuple(range(n)))
+
+
 def plus_with_minus(n: int) -> str:
     """|+ ... + - + ... +> with the single '-' on qubit n // 2."""
     return "+" * (n // 2) + "-" + "+" * (n - n // 2 - 1)

@@ -163,3 +163,24 @@ def test_fused_runs_reduce_updates_but_not_the_state():
                      if len(p.terms[t.rows[g % t.l_eff].term].qubits) == 2)
     gate_updates = sum(1 for o in ops if o[0] == "update" and not np.allclose(o[2], schedule.SWAP4))
     assert gate_updates < n_two_site
+
+
+def test_transfer_contraction_on_random_state_matches_dense():
+    # an entangled state with no structure: every bond at its maximum (or the
+    # cap) and every Schmidt spectrum generic, so a dropped term, a swapped
+    # index or a missing conjugate in the contraction shows
+    n = 9
+    init = ti.random_mps(n, 12, seed=4)
+    assert init.bonds() == (1, 2, 4, 8, 12, 12, 8, 4, 2, 1)
+    for k, A in enumerate(init.tensors[1:], start=1):
+        M = A.reshape(A.shape[0], -1)
+        assert np.allclose(M @ M.conj().T, np.eye(A.shape[0]), atol=1e-13)
+    m = MPS.from_initial(init)
+    psi = m.to_dense()
+    assert abs(np.vdot(psi, psi).real - 1.0) < 1e-13
+    psi = psi.reshape((2,) * n)
+    obs = ti.xyz_all(n) + (ti.zz(0, 5), ti.half_ring_zz(n),
+                           (ti.PauliString("XY", (2, 7), 0.3), ti.PauliString("ZZ", (1, 8), -1.1)))
+    qa = tuple(range(n))
+    for o in obs:
+        assert abs(observable_value(m, qa, o) - dense.expectation(psi, o)) < 1e-13

@@ -84,7 +84,7 @@ def parse():
     ap.add_argument("--no-pi", action="store_true",
                     help="hybrid workload: the biased variant without pi rotations")
     ap.add_argument("--cycle-caps", action="store_true",
-                    help="hybrid workload: caps 16, 32, 64 in turn instead of largest first")
+                    help="hybrid workload: caps 16, 32, 64 in turn instead of by thirds")
     ap.add_argument("--read-every", type=int, default=100,
                     help="truncation workload: Trotter steps between read-outs")
     ap.add_argument("--delta-log2", type=int, default=12,
@@ -313,9 +313,9 @@ def hybrid_segment(n_samples, no_pi, initial_mps=None, cycled=False):
     """The TE-PAI segment of the combined long-time configuration: the n = 100
     Heisenberg ring (h ~ U[-1,1]), T = 2, N = 1024, Delta = pi/512, bond caps
     64, 32 and 16 for the first, second and last third of the samples, <Z_i>
-    and the half-ring sum of Z_i Z_{i+1}.  Workgroups start in sample order,
-    so the largest caps (the longest work) start first and the small-cap
-    samples fill the CUs that free up."""
+    and the half-ring sum of Z_i Z_{i+1}.  The library starts the samples by
+    decreasing cap whatever their order, so the longest work starts first
+    and the small-cap samples fill the CUs that free up."""
     import tepai_inputs as ti
     if cycled:      # 16, 32, 64 in turn (for comparison)
         caps = tuple((16, 32, 64)[s % 3] for s in range(n_samples))

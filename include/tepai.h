@@ -83,7 +83,10 @@ enum { TEPAI_TROTTER = 2u };
 /* Storage / arithmetic precision of the MPS path.
  * TEPAI_FP64: complex128 site tensors and FP64 throughout; per-sample values
  *   agree with an exact-arithmetic evaluation of the same truncated
- *   trajectory to about 1e-10.
+ *   trajectory to about 1e-10.  Where a bond-cap cut falls between singular
+ *   values a relative gap g apart, the kept vectors are fixed only to about
+ *   1e-15 sqrt(2 chi) / g (the Jacobi's rotation threshold over the gap),
+ *   and values may differ by that much.
  * TEPAI_FP32_MIXED: complex64 site tensors; the two-site contraction, the
  *   centre-shift products and the projection onto the kept singular vectors
  *   run on FP32 matrix cores with FP32 accumulation; the QR preconditioner,

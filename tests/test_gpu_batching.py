@@ -34,20 +34,19 @@ def handle():
     return L.Handle(0)
 
 
-def test_batching_caps_32_64_128(handle):
-    p = ti.config(3)
-    p = p.with_(n_samples=COUNT, chi_per_sample=p.chi_per_sample[:COUNT])
-    caps = p.chi_per_sample
-    assert caps == (32, 64, 128, 32, 64, 128)
-    print("batching: xxz n=64, caps 32/64/128, 16 steps, fp64 and mixed", flush=True)
-    v64, w64, s64 = gpu_batch(handle, p, 0, COUNT, [STEPS // 2, STEPS // 2])
-    vmx, wmx, smx = run_batch(handle, p, COUNT, [STEPS], L.TEPAI_FP32_MIXED)
+def check_both_precisions(handle, p, steps, windows):
+    """Run p's samples in one FP64 and one mixed batch and compare each with
+    one oracle pass; returns the number of samples compared by value."""
+    count = p.n_samples
+    caps = p.chi_per_sample or (p.chi_max,) * count
+    v64, w64, s64 = gpu_batch(handle, p, 0, count, windows)
+    vmx, wmx, smx = run_batch(handle, p, count, [steps], L.TEPAI_FP32_MIXED)
     assert np.array_equal(w64, wmx)
     t = pai.build_table(p)
-    lg = t.log_g1(STEPS)
+    lg = t.log_g1(steps)
     compared = 0
-    for s in range(COUNT):
-        r = run_sample(p, t, s, STEPS)
+    for s in range(count):
+        r = run_sample(p, t, s, steps)
         for st in (s64, smx):
             assert int(st["n_gates"][s]) == r.n_gates
             assert int(st["sign"][s]) == r.sign
@@ -77,4 +76,12 @@ def test_batching_caps_32_64_128(handle):
         assert e64 <= value_tol(r), (s, e64)
         assert emx <= TOL_MIXED, (s, emx)
         compared += 1
-    assert compared >= 2
+    return compared
+
+
+def test_batching_caps_32_64_128(handle):
+    p = ti.config(3)
+    p = p.with_(n_samples=COUNT, chi_per_sample=p.chi_per_sample[:COUNT])
+    assert p.chi_per_sample == (32, 64, 128, 32, 64, 128)
+    print("batching: xxz n=64, caps 32/64/128, 16 steps, fp64 and mixed", flush=True)
+    assert check_both_precisions(handle, p, STEPS, [STEPS // 2, STEPS // 2]) >= 2

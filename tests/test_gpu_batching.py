@@ -73,7 +73,7 @@ def check_both_precisions(handle, p, steps, windows):
             assert emx <= TOL_MIXED + bmx, (s, emx, bmx)
             continue
         print(f"  fp64 err {e64:.2e}, mixed err {emx:.2e}", flush=True)
-        assert e64 <= value_tol(r), (s, e64)
+        assert e64 <= value_tol(r, cap=caps[s]), (s, e64)
         assert emx <= TOL_MIXED, (s, emx)
         compared += 1
     return compared

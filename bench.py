@@ -197,7 +197,7 @@ def run_path(L, h, p, precision, J, K, W, B):
     s1 = b.stats()
     evolve_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs)
     d = {f: float(np.sum(s1[f].astype(np.float64) - s0[f].astype(np.float64)))
-         for f in ("n_gates", "updates", "shifts", "nominal_flops", "jacobi_sweeps")}
+         for f in ("n_gates", "updates", "shifts", "nominal_flops", "jacobi_sweeps", "sum_chi3")}
     achieved = d["nominal_flops"] / (evolve_ms / 1e3) / 1e12
     return {
         "value": B * K * J / p.trotter_steps / wall,
@@ -205,6 +205,7 @@ def run_path(L, h, p, precision, J, K, W, B):
         "ms_per_step": wall / K * 1e3,
         "gates_per_s": d["n_gates"] / wall,
         "updates_per_s": d["updates"] / wall,
+        "sum_chi3_per_s": d["sum_chi3"] / wall,
         "mean_max_bond": float(np.mean(s1["max_bond"])),
         "sweeps": d["jacobi_sweeps"] / max(1.0, d["updates"] + d["shifts"]),
         "achieved": achieved,
@@ -494,10 +495,12 @@ def main():
                    "path": "batched mixed precision (one workgroup per sample, fused sampler)"},
         "gates_per_s": mixed["gates_per_s"],
         "updates_per_s": mixed["updates_per_s"],
+        "sum_chi3_per_s": mixed["sum_chi3_per_s"],
         "mean_max_bond": mixed["mean_max_bond"],
         "jacobi_sweeps_per_factorisation": mixed["sweeps"],
         "plain_fp64": {"value": plain["value"], "unit": "samples/s", "dtype": "c128 (f64)",
                        "ms_per_step": plain["ms_per_step"], "gates_per_s": plain["gates_per_s"],
+                       "sum_chi3_per_s": plain["sum_chi3_per_s"],
                        "jacobi_sweeps_per_factorisation": plain["sweeps"],
                        "kernel_ms_per_launch": plain["kernel_ms_per_launch"],
                        "achieved_tflops": plain["achieved"],

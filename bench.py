@@ -434,7 +434,7 @@ def hybrid_experiment(L, h, a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     if a.copy_probe:
         copy_probe(a.copy_probe)

@@ -9,6 +9,22 @@ to the chi largest singular values at each two-site update; LAPACK's SVD
 
 Per-update bookkeeping (for the cost model C_circ ~ sum_m chi_m^3 of eq.
 Wsample) records the bond dimensions of every update.
+
+Near-ties at a cut made by the bond cap (the paper does not discuss them):
+the singular vectors straddling a cut between sigma_{k-1} and sigma_k are
+fixed by FP64 arithmetic only to an angle theta = min(1, eps / g), with g =
+(sigma_{k-1} - sigma_k) / sigma_0 the gap and eps = u sqrt(R C) a backward
+error of an SVD of the R x C matrix relative to sigma_0 (u = 2^-53; Wedin's
+sin-theta theorem).  Turning the kept subspace by theta moves the normalised
+truncated state by at most sqrt(2) theta sigma_{k-1} / |sigma_kept|, so two
+SVDs that both meet that error bound give states within twice that, and an
+observable of unit norm differs by at most
+    B = 4 sqrt(2) theta sigma_{k-1} / |sigma_kept|.
+A cut whose B exceeds 1e-10 (FP64 cannot fix its truncated state to the
+1e-10 bar) counts as a tie.  B is local: a later cut amplifies a difference
+that earlier rounding left, so the sensitivity of a whole trajectory is
+measured instead by running it again with every factorised matrix perturbed
+at the level of an SVD's backward error (``perturb``).
 """
 from __future__ import annotations
 
@@ -29,6 +45,24 @@ class Stats:
     max_discarded: float = 0.0
     ties: int = 0
     min_gap: float = np.inf
+    flags: int = 0                 # NONFINITE: a factorisation met a non-finite value
+
+
+NONFINITE = 1
+U_ROUND = 2.0 ** -53
+TIE_BOUND = 1e-10
+
+
+def cut_sensitivity(S: np.ndarray, k: int, rows: int, cols: int, eps=None) -> float:
+    """Bound B on how far two SVDs may move a unit-norm observable through the
+    cut between S[k-1] and S[k] (S descending; see the module docstring);
+    eps is the SVDs' backward error relative to S[0], u sqrt(rows cols) for
+    FP64 by default."""
+    gap = (S[k - 1] - S[k]) / S[0]
+    if eps is None:
+        eps = U_ROUND * np.sqrt(float(rows) * float(cols))
+    theta = 1.0 if gap <= eps else eps / gap
+    return 4.0 * np.sqrt(2.0) * theta * S[k - 1] / np.linalg.norm(S[:k])
 
 
 def svd_flops(m: int, n: int) -> float:
@@ -48,7 +82,13 @@ def nominal_update_flops(chi_l: int, chi_m: int, chi_r: int) -> float:
 
 
 class MPS:
-    def __init__(self, bits: str, cutoff: float = 1e-12):
+    """``perturb = (seed, scale)``: before every factorisation add a random
+    complex matrix of Frobenius norm scale * u * sqrt(R C) * |M|_F to the
+    R x C matrix M (a backward error of that size; scale 1 for FP64 and
+    2^29 for FP32 rounding), to measure how sensitive the trajectory is to
+    rounding."""
+
+    def __init__(self, bits: str, cutoff: float = 1e-12, perturb=None):
         self.n = len(bits)
         self.A: List[np.ndarray] = []
         for b in bits:
@@ -58,11 +98,14 @@ class MPS:
         self.centre = 0
         self.cutoff = cutoff
         self.stats = Stats()
+        self.perturb = None
+        if perturb is not None:
+            self.perturb = (np.random.default_rng(perturb[0]), float(perturb[1]))
 
     @classmethod
-    def from_initial(cls, init, cutoff: float = 1e-12) -> "MPS":
+    def from_initial(cls, init, cutoff: float = 1e-12, perturb=None) -> "MPS":
         """A copy of a given mixed-canonical MPS (site order as given)."""
-        m = cls("0" * len(init.tensors), cutoff)
+        m = cls("0" * len(init.tensors), cutoff, perturb)
         m.A = [np.array(a, dtype=complex, copy=True) for a in init.tensors]
         m.centre = init.centre
         return m
@@ -71,6 +114,21 @@ class MPS:
     def apply_local(self, site: int, U: np.ndarray):
         self.A[site] = np.einsum("st,atb->asb", U, self.A[site])
         self.stats.locals += 1
+
+    def _svd(self, M: np.ndarray):
+        """LAPACK's SVD; a matrix with a non-finite entry flags the sample and
+        gives a rank-one NaN factorisation (its values become NaN)."""
+        if not np.all(np.isfinite(M)):
+            self.stats.flags |= NONFINITE
+            m, n = M.shape
+            return (np.full((m, 1), np.nan, dtype=complex), np.array([np.nan]),
+                    np.full((1, n), np.nan, dtype=complex))
+        if self.perturb is not None:
+            rng, scale = self.perturb
+            E = rng.standard_normal(M.shape) + 1j * rng.standard_normal(M.shape)
+            size = scale * U_ROUND * np.sqrt(float(M.size)) * np.linalg.norm(M)
+            M = M + E * (size / np.linalg.norm(E))
+        return np.linalg.svd(M, full_matrices=False)
 
     def _keep(self, S: np.ndarray) -> int:
         if S.size == 0 or S[0] == 0.0:
@@ -83,12 +141,12 @@ class MPS:
         A = self.A[c]
         cl, _, cr = A.shape
         if d > 0:
-            U, S, Vh = np.linalg.svd(A.reshape(cl * 2, cr), full_matrices=False)
+            U, S, Vh = self._svd(A.reshape(cl * 2, cr))
             k = max(self._keep(S), 1)
             self.A[c] = U[:, :k].reshape(cl, 2, k)
             self.A[c + 1] = np.einsum("kb,bsc->ksc", S[:k, None] * Vh[:k], self.A[c + 1])
         else:
-            U, S, Vh = np.linalg.svd(A.reshape(cl, 2 * cr), full_matrices=False)
+            U, S, Vh = self._svd(A.reshape(cl, 2 * cr))
             k = max(self._keep(S), 1)
             self.A[c] = Vh[:k].reshape(k, 2, cr)
             self.A[c - 1] = np.einsum("asb,bk->ask", self.A[c - 1], U[:, :k] * S[None, :k])
@@ -102,7 +160,7 @@ class MPS:
         cl, cm, cr = A.shape[0], A.shape[2], B.shape[2]
         theta = np.einsum("asb,btc->astc", A, B)
         theta = np.einsum("uvst,astc->auvc", G.reshape(2, 2, 2, 2), theta)
-        U, S, Vh = np.linalg.svd(theta.reshape(2 * cl, 2 * cr), full_matrices=False)
+        U, S, Vh = self._svd(theta.reshape(2 * cl, 2 * cr))
         r = max(self._keep(S), 1)
         k = min(chi, r)
         tot = float(np.sum(S * S))
@@ -115,10 +173,10 @@ class MPS:
         st.max_discarded = max(st.max_discarded, disc)
         if k < r:
             # a cut made by the bond cap: the kept state is unique only when
-            # sigma_{k-1} > sigma_k; record the gap and flag near-ties
+            # sigma_{k-1} > sigma_k; record the gap and the cut's sensitivity
             gap = (S[k - 1] - S[k]) / S[0]
             st.min_gap = min(st.min_gap, gap)
-            if gap <= 1e-10:
+            if cut_sensitivity(S, k, 2 * cl, 2 * cr) > TIE_BOUND:
                 st.ties += 1
         Sk = S[:k] / np.linalg.norm(S[:k])
         if right:

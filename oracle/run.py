@@ -60,7 +60,10 @@ def observable_value(mps: MPS, qubit_at, observable) -> float:
     return tot
 
 
-def run_sample(problem, table, s: int, layers: Optional[int] = None) -> SampleResult:
+def run_sample(problem, table, s: int, layers: Optional[int] = None,
+               perturb=None) -> SampleResult:
+    """One sample; ``perturb = (seed, scale)`` perturbs every factorisation at
+    the level of an SVD backward error (see ``mps.MPS``)."""
     if getattr(problem, "trotter", False):
         steps = problem.trotter_steps if layers is None else layers
         circ = product_formula_circuit(table, steps, s)
@@ -68,8 +71,8 @@ def run_sample(problem, table, s: int, layers: Optional[int] = None) -> SampleRe
         circ = sample_circuit(problem, table, s, layers)
     ops, qubit_at = build_schedule(problem, table, circ, chi_of(problem, s))
     init = getattr(problem, "initial_mps", None)
-    mps = (MPS.from_initial(init, problem.svd_cutoff) if init is not None
-           else MPS(problem.initial_bits, problem.svd_cutoff)).run(ops)
+    mps = (MPS.from_initial(init, problem.svd_cutoff, perturb) if init is not None
+           else MPS(problem.initial_bits, problem.svd_cutoff, perturb)).run(ops)
     vals = np.array([observable_value(mps, qubit_at, o) for o in problem.observables])
     return SampleResult(sample=s, sign=circ.sign, n_gates=circ.n_gates, values=vals,
                         stats=mps.stats, bonds=mps.bonds())

@@ -13,7 +13,9 @@ every path that claims parity with this oracle:
    either qubit in between and within one Trotter step, are multiplied into
    one 4x4 operator and applied as ONE two-site update (one truncated SVD).  A run made only of pi
    rotations (C = -i P (x) P) is a product of local unitaries and is applied
-   to the two site tensors without an SVD.
+   to the two site tensors without an SVD.  With ``problem.per_gate`` every
+   run holds a single gate: each sampled two-qubit gate is its own truncated
+   update (a pi rotation its own pair of local Paulis).
 3. A two-qubit operator whose qubits sit on non-adjacent sites lo < hi (on a
    ring kept as a chain these are the chain's two ends) is routed with SWAPs
    and the chain is left in its new order: the end qubit nearer the
@@ -162,6 +164,7 @@ def build_schedule(problem, table, circuit, chi: Optional[int] = None) -> Tuple[
         qubit_at[at], qubit_at[at + 1] = b, a
         site_of[a], site_of[b] = at + 1, at
 
+    per_gate = bool(getattr(problem, "per_gate", False))
     pending: Optional[_Pending] = None
     for g, setting in zip(circuit.draws.tolist(), circuit.settings.tolist()):
         layer = g // L
@@ -196,5 +199,8 @@ def build_schedule(problem, table, circuit, chi: Optional[int] = None) -> Tuple[
             pending.La = PAULI[pa] @ pending.La
             pending.Lb = PAULI[pb] @ pending.Lb
             pending.phase *= -1j
+        if per_gate:
+            flush(pending)
+            pending = None
     flush(pending)
     return ops, qubit_at

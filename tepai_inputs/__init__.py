@@ -90,6 +90,7 @@ class Problem:
     chi_per_sample: Optional[Tuple[int, ...]] = None
     no_pi: bool = False         # biased variant without pi rotations
     trotter: bool = False       # deterministic product formula: every rotation exact
+    per_gate: bool = False      # every sampled two-qubit gate its own truncated update
     initial_mps: Optional[InitialMPS] = None   # start every sample from this state
     name: str = ""
 

@@ -184,3 +184,152 @@ def test_transfer_contraction_on_random_state_matches_dense():
     qa = tuple(range(n))
     for o in obs:
         assert abs(observable_value(m, qa, o) - dense.expectation(psi, o)) < 1e-13
+
+
+# ---------------------------------------------------------------- accounting
+@pytest.mark.parametrize("chi", [1, 2, 16, 128, 256])
+def test_nominal_update_flops_uniform_chi_is_704_chi_cubed(chi):
+    """At uniform bond chi the per-update count is 32 chi^3 for the
+    (2chi x chi)(chi x 2chi) complex contraction plus the Golub-Reinsch SVD
+    of the 2chi x 2chi result, 4 (4 + 8 + 9) (2chi)^3 = 672 chi^3."""
+    from oracle.mps import nominal_update_flops, svd_flops
+    assert nominal_update_flops(chi, chi, chi) == 704.0 * chi ** 3
+    assert svd_flops(2 * chi, 2 * chi) == 672.0 * chi ** 3
+    # thin SVD of a tall matrix: 4 (4 m^2 n + 8 m n^2 + 9 n^3), either orientation
+    assert svd_flops(6, 2) == svd_flops(2, 6) == 4 * (4 * 36 * 2 + 8 * 6 * 4 + 9 * 8)
+
+
+def test_sum_chi3_and_flops_follow_the_update_log():
+    """The counters add chi_mid^3 and the nominal count of every update, in
+    the order the updates run (replayed here from the operation list)."""
+    from oracle.mps import nominal_update_flops
+    p = ti.small_ring(8, seed=4, T=0.4, N=6, delta=math.pi / 16, chi=4, n_samples=1)
+    t = pai.build_table(p)
+    c = sampler.sample_circuit(p, t, 0)
+    ops, _ = schedule.build_schedule(p, t, c)
+    m = MPS(p.initial_bits, p.svd_cutoff)
+    chi3, flops, n = 0.0, 0.0, 0
+    for op in ops:
+        if op[0] == "update":
+            i = op[1]
+            cl, cm, cr = m.A[i].shape[0], m.A[i].shape[2], m.A[i + 1].shape[2]
+            chi3 += float(cm) ** 3
+            flops += nominal_update_flops(cl, cm, cr)
+            n += 1
+        m.run([op])
+    assert n == m.stats.updates > 0
+    assert m.stats.sum_chi3 == chi3 and m.stats.nominal_flops == flops
+
+
+# ------------------------------------------------------------- near-ties
+def _unitary(n, rng):
+    q, r = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def _truncated_state(M, k):
+    U, S, Vh = np.linalg.svd(M, full_matrices=False)
+    psi = (U[:, :k] * S[:k]) @ Vh[:k]
+    return psi.reshape(-1) / np.linalg.norm(S[:k])
+
+
+@pytest.mark.parametrize("s_cut", [0.3, 1e-3])
+@pytest.mark.parametrize("gap", [1e-4, 1e-6, 1e-8, 1e-10])
+def test_cut_sensitivity_bounds_truncations_of_nearby_matrices(s_cut, gap):
+    """Two matrices eta sigma_0 apart (two SVDs with backward error eta) give
+    truncated states whose expectation values, over every observable of unit
+    norm, differ by at most the cut's bound B (with eps = eta) plus the
+    direct effect of the perturbation, 4 eta / |sigma_kept|; and when the gap
+    is far below eta the straddling pair is mixed and B is attained to within
+    a small factor (so B scales with sigma_{k-1}, not with the gap alone)."""
+    from oracle.mps import cut_sensitivity
+    rng = np.random.default_rng(17)
+    R, C, k, eta = 24, 20, 8, 1e-6
+    head = np.geomspace(1.0, 3 * s_cut, k - 1)
+    tail = np.geomspace(0.5 * s_cut, 1e-3 * s_cut, C - k - 1)
+    sig = np.concatenate([head, [s_cut, s_cut - gap * 1.0], tail])
+    assert np.all(np.diff(sig) <= 0)
+    M = (_unitary(R, rng)[:, :C] * sig) @ _unitary(C, rng)
+    E = rng.standard_normal((R, C)) + 1j * rng.standard_normal((R, C))
+    E *= eta * sig[0] / np.linalg.norm(E, 2)
+    a, b = _truncated_state(M, k), _truncated_state(M + E, k)
+    worst = 2.0 * math.sqrt(max(0.0, 1.0 - abs(np.vdot(a, b)) ** 2))   # max over |O| <= 1
+    S = np.linalg.svd(M, compute_uv=False)
+    B = cut_sensitivity(S, k, R, C, eps=eta)
+    kept = np.linalg.norm(S[:k])
+    assert worst <= B + 4 * eta / kept, (worst, B)
+    if gap < 1e-2 * eta:
+        assert worst >= B / 30, (worst, B)
+
+
+def test_nonfinite_tensor_flags_the_sample():
+    """A non-finite entry (forced into an oracle tensor) flags the sample and
+    makes its values NaN instead of stopping the run."""
+    from oracle.mps import NONFINITE
+    p = ti.small_ring(6, seed=2, T=0.3, N=4, delta=math.pi / 16, chi=4, n_samples=1)
+    t = pai.build_table(p)
+    c = sampler.sample_circuit(p, t, 0)
+    ops, qa = schedule.build_schedule(p, t, c)
+    m = MPS(p.initial_bits, p.svd_cutoff)
+    m.A[2] = m.A[2].copy()
+    m.A[2][0, 0, 0] = np.nan
+    m.run(ops)
+    assert m.stats.flags & NONFINITE
+    assert math.isnan(observable_value(m, qa, p.observables[0]))
+
+
+def test_rounding_sensitivity_run():
+    """The perturbed oracle run (a random backward error of u sqrt(R C) |M|
+    added before every factorisation) moves a well-conditioned trajectory by
+    rounding-level amounts, scales with the perturbation, and separates a
+    trajectory whose cap cut falls inside an exactly degenerate pair."""
+    # exact regime (no cap cut): the change stays at the rounding level
+    p = ti.config(1)
+    t = pai.build_table(p)
+    r = run_sample(p, t, 3)
+    d64 = np.max(np.abs(run_sample(p, t, 3, perturb=(1, 1.0)).values - r.values))
+    d32 = np.max(np.abs(run_sample(p, t, 3, perturb=(1, 2.0 ** 29)).values - r.values))
+    assert 0 < d64 < 1e-12
+    assert 1e-9 < d32 < 1e-4 and d32 > 1e5 * d64
+    # cap 2 with a doubly degenerate spectrum at the cut (the kept vector is
+    # not unique): a rounding-level perturbation moves the values at O(1e-2)
+    q = ti.small_ring(10, seed=7, T=0.4, N=10, delta=math.pi / 16, chi=8, n_samples=6)
+    q = q.with_(chi_per_sample=(2, 4, 8, 3, 8, 5))
+    tq = pai.build_table(q)
+    rq = run_sample(q, tq, 0)
+    assert rq.stats.ties > 0
+    assert np.max(np.abs(run_sample(q, tq, 0, perturb=(1, 1.0)).values - rq.values)) > 1e-6
+
+
+# ------------------------------------------------------------ per-gate mode
+def test_per_gate_mode_exact_regime_matches_dense_and_fused():
+    """One truncated update per sampled gate changes only where the
+    truncations happen: at full bond dimension the state equals the dense
+    state of the same sampled circuit, and the fused schedule's."""
+    p = ti.config(1).with_(per_gate=True)
+    t = pai.build_table(p)
+    for s in (0, 4):
+        c, ops, qa, m = mps_for(p, t, s)
+        psi_m = qubit_state(m, qa).reshape(-1)
+        psi_c = dense.circuit_state(p, t, c).reshape(-1)
+        assert np.max(np.abs(psi_m - psi_c)) < 1e-12
+        _, ops_f, qa_f, m_f = mps_for(p.with_(per_gate=False), t, s)
+        assert np.max(np.abs(qubit_state(m_f, qa_f).reshape(-1) - psi_m)) < 1e-12
+
+
+def test_per_gate_update_count_is_one_per_b_gate_plus_routing():
+    """Every sampled B setting on a qubit pair is one two-site update; the
+    wrap pair adds hi - lo - 1 SWAP updates when its qubits are not adjacent;
+    C settings on pairs cost no update."""
+    p = ti.small_ring(8, seed=6, T=0.5, N=8, delta=math.pi / 16, chi=4, n_samples=1)
+    pg = p.with_(per_gate=True)
+    t = pai.build_table(p)
+    c = sampler.sample_circuit(p, t, 0)
+    ops_g, _ = schedule.build_schedule(pg, t, c)
+    ops_f, _ = schedule.build_schedule(p, t, c)
+    n_b2 = sum(1 for g, st in zip(c.draws.tolist(), c.settings.tolist())
+               if st == sampler.SET_B and len(p.terms[t.rows[g % t.l_eff].term].qubits) == 2)
+    swaps = sum(1 for op in ops_g if op[0] == "update" and np.allclose(op[2], schedule.SWAP4))
+    n_upd = sum(1 for op in ops_g if op[0] == "update")
+    assert n_upd == n_b2 + swaps
+    assert n_upd > sum(1 for op in ops_f if op[0] == "update")

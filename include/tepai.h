@@ -31,10 +31,15 @@
  *  - a rotation with |theta_k| > Delta is split into m = ceil(|theta_k|/Delta)
  *    equal sub-rotations (the paper assumes |theta| <= Delta);
  *  - consecutive sampled gates on one qubit pair form one two-site update
- *    (one truncated SVD); runs end at Trotter-step boundaries;
- *  - a two-qubit gate on non-adjacent sites (the ring's wrap bond) is
- *    applied by carrying the upper qubit down with SWAP updates (each
- *    truncated) and back up again;
+ *    (one truncated SVD); runs end at Trotter-step boundaries
+ *    (TEPAI_PER_GATE: one update per sampled gate instead);
+ *  - a two-qubit gate on non-adjacent sites lo < hi (the ring's wrap bond,
+ *    once the ring is kept as a chain) is applied by carrying the end qubit
+ *    nearer the orthogonality centre across the chain with truncated SWAP
+ *    updates, the last of which is SWAP.G on the pair: hi - lo updates per
+ *    routed gate, no return trip, and the chain keeps its new order (a
+ *    rotation of the ring by one site, which tepai_batch_read_mps reports
+ *    in qubit_at);
  *  - a two-site update keeps min(chi, #{sigma_i > svd_cutoff * sigma_0})
  *    singular values and renormalises them; the orthogonality centre is
  *    moved by single-site SVDs that drop sigma_i <= svd_cutoff * sigma_0.
@@ -55,8 +60,16 @@ typedef enum {
   TEPAI_ERANGE = -2,    /* value out of range (Delta not in (0,pi), N = 0, chi = 0 ...) */
   TEPAI_ENOMEM = -3,    /* workspace or output capacity too small */
   TEPAI_EDEVICE = -4,   /* HIP runtime error */
-  TEPAI_ENUMERIC = -5   /* non-finite result */
+  TEPAI_ENUMERIC = -5   /* a sample met a non-finite value or a factorisation hit the
+                           Jacobi sweep cap (its tepai_sample_stats.flags say which),
+                           or an estimate is not finite; outputs are still written */
 } tepai_status;
+
+/* tepai_sample_stats.flags bits. */
+enum {
+  TEPAI_SAMPLE_NONFINITE = 1u,      /* a factorisation saw a non-finite or zero norm */
+  TEPAI_SAMPLE_NONCONVERGED = 2u    /* a Jacobi SVD stopped at the sweep cap */
+};
 
 enum { TEPAI_PAULI_I = 0, TEPAI_PAULI_X = 1, TEPAI_PAULI_Y = 2, TEPAI_PAULI_Z = 3 };
 
@@ -79,19 +92,29 @@ enum { TEPAI_NO_PI = 1u };
  *   TEPAI_SET_B (here meaning the exact rotation), every sign is +1 and every
  *   weight is 1.  Cannot be combined with TEPAI_NO_PI. */
 enum { TEPAI_TROTTER = 2u };
+/* TEPAI_PER_GATE: every sampled two-qubit gate is applied as its own
+ *   truncated two-site update (a pi rotation as local Paulis, without an
+ *   SVD) instead of fusing a run of consecutive gates on one qubit pair into
+ *   one update.  It changes the truncation points, not the circuit: with no
+ *   truncation both forms give the same state.  Combines with the other
+ *   flags. */
+enum { TEPAI_PER_GATE = 4u };
 
 /* Storage / arithmetic precision of the MPS path.
- * TEPAI_FP64: complex128 site tensors and FP64 throughout; per-sample values
- *   agree with an exact-arithmetic evaluation of the same truncated
- *   trajectory to about 1e-10.  Where a bond-cap cut falls between singular
- *   values a relative gap g apart, the kept vectors are fixed only to about
- *   1e-15 sqrt(2 chi) / g (the Jacobi's rotation threshold over the gap),
- *   and values may differ by that much.
+ * TEPAI_FP64: complex128 site tensors and FP64 throughout (the Jacobi skips
+ *   a column pair only below 2^-53 sqrt(R) of its norms, LAPACK's one-sided
+ *   Jacobi criterion); per-sample values agree with another FP64 evaluation
+ *   of the same truncated trajectory to about 1e-10, unless the trajectory
+ *   itself is sensitive to rounding: a cut at the bond cap between nearly
+ *   equal singular values (counted in tepai_sample_stats.ties) lets rounding
+ *   decide which straddling vector is kept, and later cuts amplify earlier
+ *   rounding differences by about sigma_{k-1} / gap.
  * TEPAI_FP32_MIXED: complex64 site tensors; the two-site contraction, the
  *   centre-shift products and the projection onto the kept singular vectors
  *   run on FP32 matrix cores with FP32 accumulation; the QR preconditioner,
- *   the Jacobi orthogonalisation (stopped once a sweep turns no pair by more
- *   than |tan| = 1e-5, the FP64 path uses 1e-8), the truncation, the
+ *   the Jacobi orthogonalisation (stopped after a sweep in which every
+ *   rotated column pair had a cosine |x^H y| / (|x||y|) <= 1e-5; the FP64
+ *   path uses 1e-8), the truncation, the
  *   renormalisation, the weights and the estimator stay FP64.  Per-sample
  *   values agree with the FP64 path to about 1e-4. */
 enum { TEPAI_FP64 = 0, TEPAI_FP32_MIXED = 1 };
@@ -123,7 +146,9 @@ typedef struct {
  * row-major, as interleaved (re, im) doubles; the sites are concatenated in
  * order.  qubit_at[k] is the qubit held at site k (NULL: qubit k).  Sites
  * left of `centre` must be left-canonical and sites right of it
- * right-canonical (not checked: truncations are optimal only in that form).
+ * right-canonical (not checked: truncations are optimal only in that form;
+ * nor are the values checked: a non-finite entry makes every sample
+ * non-finite, which tepai_run reports as TEPAI_ENUMERIC).
  * bond[0] = bond[n] = 1, and no bond may exceed the smallest bond cap of the
  * samples.  Caller-owned; the library copies it in tepai_batch_create (and
  * tepai_run) and keeps no pointer. */
@@ -149,13 +174,13 @@ typedef struct {
   const uint32_t* chi_per_sample; /* nullable; [n_samples] caps <= chi_max */
   double svd_cutoff;            /* relative singular-value floor, >= 0 (the mixed
                                    path uses max(svd_cutoff, 1e-7)) */
-  const uint8_t* initial_bits;  /* [n_qubits] computational-basis start, 0/1
-                                   (ignored when initial_mps is given) */
+  const uint8_t* initial_bits;  /* [n_qubits] computational-basis start, 0/1;
+                                   ignored (and may be NULL) when initial_mps is given */
   uint32_t n_obs;
   uint32_t n_strings;
   const tepai_pauli_string* strings;
   uint32_t precision;           /* TEPAI_FP64 or TEPAI_FP32_MIXED */
-  uint32_t flags;               /* 0, TEPAI_NO_PI or TEPAI_TROTTER */
+  uint32_t flags;               /* TEPAI_NO_PI or TEPAI_TROTTER, | TEPAI_PER_GATE */
   const tepai_mps* initial_mps; /* NULL: start from initial_bits */
 } tepai_problem;
 
@@ -167,7 +192,10 @@ typedef struct {
   uint64_t shifts;              /* single-site centre shifts */
   uint64_t jacobi_sweeps;       /* over all factorisations */
   uint64_t nonconverged;        /* factorisations that hit the sweep cap */
-  uint64_t ties;                /* updates with sigma_{k-1}-sigma_k <= 1e-10 sigma_0 at a chi cut */
+  uint64_t ties;                /* near ties: cap cuts where 4 sqrt(2) th sigma_{k-1} / |sigma_kept|
+                                   > 1e-10, th = min(1, eps / gap), gap = (sigma_{k-1} -
+                                   sigma_k) / sigma_0, eps = 2^-53 sqrt(R C) for an R x C
+                                   matrix: FP64 rounding does not fix the kept state there */
   double sum_chi3;              /* sum over updates of chi_mid^3 */
   double nominal_flops;         /* Golub-Reinsch count of all updates */
   double discarded;             /* sum of discarded squared Schmidt weight */
@@ -176,7 +204,7 @@ typedef struct {
   int32_t sign;                 /* (-1)^(number of C settings) */
   uint32_t layer;               /* Trotter steps applied so far */
   uint32_t max_bond;
-  uint32_t flags;               /* bit 0: non-finite value seen */
+  uint32_t flags;               /* TEPAI_SAMPLE_NONFINITE | TEPAI_SAMPLE_NONCONVERGED */
 } tepai_sample_stats;
 
 typedef struct tepai_handle tepai_handle;
@@ -270,8 +298,11 @@ tepai_status tepai_reduce(tepai_handle* h, uint64_t count, uint32_t n_obs, const
 
 /* The whole estimator, synchronous, host outputs: mean[n_obs], std_err[n_obs],
  * weights[n_samples]; values[n_samples * n_obs] and stats[n_samples] are
- * optional (NULL to skip).  Allocates and frees its own device memory and
- * processes the samples in batches of at most `batch` (0 = library choice). */
+ * optional (NULL to skip).  Allocates and frees its own device memory (freed
+ * on every return path) and processes the samples in batches of at most
+ * `batch` (0 = library choice).  Returns TEPAI_ENUMERIC, with every output
+ * written, when a sample's flags are set (non-finite value, Jacobi sweep cap)
+ * or an estimate is not finite. */
 tepai_status tepai_run(tepai_handle* h, const tepai_problem* p, uint32_t batch, double* mean,
                        double* std_err, double* weights, double* values,
                        tepai_sample_stats* stats);

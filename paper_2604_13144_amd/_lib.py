@@ -24,6 +24,10 @@ TEPAI_FP64 = 0
 TEPAI_FP32_MIXED = 1
 TEPAI_NO_PI = 1
 TEPAI_TROTTER = 2
+TEPAI_PER_GATE = 4
+TEPAI_ENUMERIC = -5
+TEPAI_SAMPLE_NONFINITE = 1
+TEPAI_SAMPLE_NONCONVERGED = 2
 
 
 class tepai_term(C.Structure):
@@ -189,7 +193,8 @@ class ProblemStruct:
         s.strings = C.cast(self._strings, C.POINTER(tepai_pauli_string))
         s.precision = int(precision)
         s.flags = ((TEPAI_NO_PI if getattr(p, "no_pi", False) else 0)
-                   | (TEPAI_TROTTER if getattr(p, "trotter", False) else 0))
+                   | (TEPAI_TROTTER if getattr(p, "trotter", False) else 0)
+                   | (TEPAI_PER_GATE if getattr(p, "per_gate", False) else 0))
         init = getattr(p, "initial_mps", None)
         s.initial_mps = None
         if init is not None:
@@ -403,7 +408,10 @@ def tepai_reduce(h: Handle, count: int, n_obs: int, d_values, d_weights, d_mean,
 
 def tepai_run(h: Handle, ps: ProblemStruct, batch: int = 0, want_values: bool = True,
               want_stats: bool = True):
-    """Synchronous estimator; returns dict(mean, std_err, weights, values, stats)."""
+    """Synchronous estimator; returns dict(mean, std_err, weights, values, stats).
+
+    On TEPAI_ENUMERIC the library has still written every output: the raised
+    TepaiError carries them as ``.result``."""
     p = ps.struct
     ns, no = int(p.n_samples), int(p.n_obs)
     mean = np.zeros(no)
@@ -411,12 +419,20 @@ def tepai_run(h: Handle, ps: ProblemStruct, batch: int = 0, want_values: bool = 
     w = np.zeros(ns)
     vals = np.zeros((ns, no)) if want_values else None
     st_arr = (tepai_sample_stats * ns)() if want_stats else None
-    _check(load().tepai_run(h.h, ps.ref(), batch, _ptr(mean), _ptr(se), _ptr(w),
-                            _ptr(vals) if vals is not None else None, st_arr), h.h)
+    st = load().tepai_run(h.h, ps.ref(), batch, _ptr(mean), _ptr(se), _ptr(w),
+                          _ptr(vals) if vals is not None else None, st_arr)
+    if st not in (TEPAI_OK, TEPAI_ENUMERIC):
+        _check(st, h.h)
     stats = None
     if st_arr is not None:
         stats = np.zeros(ns, STATS_DTYPE)
         for i in range(ns):
             for f in STATS_FIELDS:
                 stats[f][i] = getattr(st_arr[i], f)
-    return dict(mean=mean, std_err=se, weights=w, values=vals, stats=stats)
+    out = dict(mean=mean, std_err=se, weights=w, values=vals, stats=stats)
+    if st == TEPAI_ENUMERIC:
+        err = TepaiError(st, (load().tepai_last_error(h.h) or b"").decode())
+        err.result = out
+        raise err
+    return out
+

@@ -35,6 +35,32 @@ tepai_status fail(tepai_handle* h, tepai_status st, const std::string& msg) {
       return fail((h), TEPAI_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
   } while (0)
 
+// Device allocations of the synchronous calls, freed on every return path.
+struct DeviceBuffers {
+  std::vector<void*> ptrs;
+  DeviceBuffers() = default;
+  DeviceBuffers(const DeviceBuffers&) = delete;
+  DeviceBuffers& operator=(const DeviceBuffers&) = delete;
+  ~DeviceBuffers() {
+    for (void* q : ptrs) (void)hipFree(q);
+  }
+  template <typename T>
+  hipError_t alloc(T** out, size_t bytes) {
+    *out = nullptr;
+    void* q = nullptr;
+    const hipError_t e = hipMalloc(&q, bytes ? bytes : 1);
+    if (e == hipSuccess) {
+      ptrs.push_back(q);
+      *out = static_cast<T*>(q);
+    } else {
+      // reported through the status code; clear it so that it does not
+      // surface again in the caller's next launch check
+      (void)hipGetLastError();
+    }
+    return e;
+  }
+};
+
 // ------------------------------------------------------------ PAI table
 // gamma_1..3 at angle |theta| for PAI angle Delta (appendix "PAI & TE-PAI",
 // eq. gammas).
@@ -164,9 +190,12 @@ tepai_status validate(tepai_handle* h, const tepai_problem* p) {
       if (p->chi_per_sample[s] < 1 || p->chi_per_sample[s] > p->chi_max)
         return fail(h, TEPAI_ERANGE, "chi_per_sample entries must be in [1, chi_max]");
   if (!std::isfinite(p->svd_cutoff) || p->svd_cutoff < 0.0) return fail(h, TEPAI_ERANGE, "svd_cutoff must be finite and >= 0");
-  if (!p->initial_bits) return fail(h, TEPAI_EINVAL, "initial_bits is NULL");
-  for (uint32_t i = 0; i < n; ++i)
-    if (p->initial_bits[i] > 1) return fail(h, TEPAI_EINVAL, "initial_bits entries must be 0 or 1");
+  if (!p->initial_mps) {
+    // the computational-basis start is used only without a shared MPS
+    if (!p->initial_bits) return fail(h, TEPAI_EINVAL, "initial_bits is NULL and no initial_mps is given");
+    for (uint32_t i = 0; i < n; ++i)
+      if (p->initial_bits[i] > 1) return fail(h, TEPAI_EINVAL, "initial_bits entries must be 0 or 1");
+  }
   if (p->n_obs > 256) return fail(h, TEPAI_ERANGE, "at most 256 observables");
   if (p->n_strings && !p->strings) return fail(h, TEPAI_EINVAL, "strings is NULL");
   for (uint32_t s = 0; s < p->n_strings; ++s) {
@@ -200,12 +229,10 @@ tepai_status validate(tepai_handle* h, const tepai_problem* p) {
       }
     }
     if (m->reserved != 0) return fail(h, TEPAI_EINVAL, "initial_mps reserved must be 0");
-  } else if (!p->initial_bits) {
-    return fail(h, TEPAI_EINVAL, "initial_bits NULL");
   }
   if (p->precision != TEPAI_FP64 && p->precision != TEPAI_FP32_MIXED)
     return fail(h, TEPAI_EINVAL, "unsupported precision");
-  if ((p->flags & ~(uint32_t)(TEPAI_NO_PI | TEPAI_TROTTER)) != 0)
+  if ((p->flags & ~(uint32_t)(TEPAI_NO_PI | TEPAI_TROTTER | TEPAI_PER_GATE)) != 0)
     return fail(h, TEPAI_EINVAL, "unsupported flags");
   if ((p->flags & TEPAI_NO_PI) && (p->flags & TEPAI_TROTTER))
     return fail(h, TEPAI_EINVAL, "TEPAI_NO_PI and TEPAI_TROTTER exclude each other");
@@ -284,6 +311,64 @@ struct tepai_batch {
   std::vector<double2> init_tensors;
 };
 
+namespace {
+
+// The batch loop of the synchronous estimator: samples in batches of at most
+// B in the device workspace `ws`, each evolved through all N Trotter steps
+// (launches of at most 16 steps keep single kernels short), read out into
+// d_v / d_w, its per-sample counters copied to stats_out; then the weighted
+// reduction into d_m / d_se.  Work is queued on `stream` and synchronised
+// per batch.
+tepai_status run_batches(tepai_handle* h, const tepai_problem* p, uint32_t B, void* ws,
+                         size_t ws_bytes, hipStream_t stream, double* d_v, double* d_w,
+                         double* d_m, double* d_se, tepai_sample_stats* stats_out) {
+  const uint64_t ns = p->n_samples;
+  tepai_status st = TEPAI_OK;
+  for (uint64_t first = 0; first < ns && st == TEPAI_OK; first += B) {
+    const uint32_t cnt = (uint32_t)std::min<uint64_t>(B, ns - first);
+    tepai_batch* b = nullptr;
+    st = tepai_batch_create(h, p, first, cnt, ws, ws_bytes, stream, &b);
+    if (st != TEPAI_OK) break;
+    for (uint32_t done = 0; done < p->trotter_steps && st == TEPAI_OK;) {
+      const uint32_t step = std::min<uint32_t>(16, p->trotter_steps - done);
+      st = tepai_batch_evolve(b, step);
+      done += step;
+    }
+    if (st == TEPAI_OK) st = tepai_batch_observe(b, d_v + first * p->n_obs, d_w + first);
+    if (st == TEPAI_OK) st = tepai_batch_stats(b, stats_out + first);   // synchronises
+    tepai_batch_destroy(b);
+  }
+  if (st == TEPAI_OK) st = tepai_reduce(h, ns, p->n_obs, d_v, d_w, d_m, d_se, stream);
+  if (st == TEPAI_OK) {
+    const hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) st = fail(h, TEPAI_EDEVICE, std::string("estimator: ") + hipGetErrorString(e));
+  }
+  return st;
+}
+
+// TEPAI_ENUMERIC when a sample met a non-finite value or a factorisation hit
+// the sweep cap (its flags say which), or an estimate (host copy, may be NULL)
+// is not finite; the outputs are written either way.
+tepai_status numeric_status(tepai_handle* h, const tepai_problem* p,
+                            const tepai_sample_stats* stats, const double* mean) {
+  uint64_t nonfinite = 0, nonconv = 0;
+  for (uint64_t s = 0; s < p->n_samples; ++s) {
+    nonfinite += (stats[s].flags & TEPAI_SAMPLE_NONFINITE) ? 1 : 0;
+    nonconv += (stats[s].flags & TEPAI_SAMPLE_NONCONVERGED) ? 1 : 0;
+  }
+  bool bad_mean = false;
+  if (mean)
+    for (uint32_t o = 0; o < p->n_obs; ++o) bad_mean = bad_mean || !std::isfinite(mean[o]);
+  if (nonfinite || nonconv || bad_mean)
+    return fail(h, TEPAI_ENUMERIC,
+                std::to_string(nonfinite) + " sample(s) with a non-finite value, " +
+                    std::to_string(nonconv) + " with a factorisation at the sweep cap" +
+                    (bad_mean ? ", non-finite estimate" : ""));
+  return TEPAI_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 tepai_status tepai_create(tepai_handle** out, int device) {
@@ -352,13 +437,15 @@ tepai_status tepai_sample_circuits(tepai_handle* h, const tepai_problem* p, uint
   const uint64_t n_draws = (uint64_t)J * L;
   if (n_draws >= (1ull << 30)) return fail(h, TEPAI_ERANGE, "N * L_eff must be < 2^30 for gate words");
   const std::vector<DevRow> rows = device_rows(*p, t);
+  if (!words && capacity > 0) return fail(h, TEPAI_EINVAL, "words is NULL with a non-zero capacity");
   TEPAI_HIP(h, hipSetDevice(h->device));
+  DeviceBuffers bufs;
   DevRow* d_rows = nullptr;
   uint64_t* d_counts = nullptr;
   int8_t* d_signs = nullptr;
-  TEPAI_HIP(h, hipMalloc(&d_rows, sizeof(DevRow) * L));
-  TEPAI_HIP(h, hipMalloc(&d_counts, sizeof(uint64_t) * (count + 1)));
-  TEPAI_HIP(h, hipMalloc(&d_signs, count));
+  TEPAI_HIP(h, bufs.alloc(&d_rows, sizeof(DevRow) * L));
+  TEPAI_HIP(h, bufs.alloc(&d_counts, sizeof(uint64_t) * (count + 1)));
+  TEPAI_HIP(h, bufs.alloc(&d_signs, count));
   TEPAI_HIP(h, hipMemcpy(d_rows, rows.data(), sizeof(DevRow) * L, hipMemcpyHostToDevice));
   const uint64_t s0 = p->sample_offset + first;
   TEPAI_HIP(h, launch_sample_count(d_rows, L, p->seed, s0, count, n_draws, d_counts, d_signs, 0));
@@ -367,22 +454,15 @@ tepai_status tepai_sample_circuits(tepai_handle* h, const tepai_problem* p, uint
   TEPAI_HIP(h, hipMemcpy(signs, d_signs, count, hipMemcpyDeviceToHost));
   offsets[0] = 0;
   for (uint64_t i = 0; i < count; ++i) offsets[i + 1] = offsets[i] + counts[i];
-  tepai_status result = TEPAI_OK;
-  if (offsets[count] > capacity) {
-    result = fail(h, TEPAI_ENOMEM, "gate capacity too small");
-  } else if (offsets[count] > 0) {
-    if (!words) return fail(h, TEPAI_EINVAL, "words NULL");
+  if (offsets[count] > capacity) return fail(h, TEPAI_ENOMEM, "gate capacity too small");
+  if (offsets[count] > 0) {
     uint32_t* d_words = nullptr;
     TEPAI_HIP(h, hipMemcpy(d_counts, offsets, sizeof(uint64_t) * count, hipMemcpyHostToDevice));
-    TEPAI_HIP(h, hipMalloc(&d_words, sizeof(uint32_t) * offsets[count]));
+    TEPAI_HIP(h, bufs.alloc(&d_words, sizeof(uint32_t) * offsets[count]));
     TEPAI_HIP(h, launch_sample_write(d_rows, L, p->seed, s0, count, n_draws, d_counts, d_words, 0));
     TEPAI_HIP(h, hipMemcpy(words, d_words, sizeof(uint32_t) * offsets[count], hipMemcpyDeviceToHost));
-    TEPAI_HIP(h, hipFree(d_words));
   }
-  TEPAI_HIP(h, hipFree(d_rows));
-  TEPAI_HIP(h, hipFree(d_counts));
-  TEPAI_HIP(h, hipFree(d_signs));
-  return result;
+  return TEPAI_OK;
 }
 
 tepai_status tepai_workspace_size(tepai_handle* h, const tepai_problem* p, uint32_t count,
@@ -430,7 +510,7 @@ tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_
     }
     b->strings[s] = d;
   }
-  if (p->initial_bits)
+  if (p->initial_bits && !p->initial_mps)
     b->bits.assign(p->initial_bits, p->initial_bits + p->n_qubits);
   else
     b->bits.assign(p->n_qubits, 0);
@@ -465,6 +545,8 @@ tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_
   // spectrum; the mixed path does not count it as Schmidt rank
   a.cutoff = a.mixed ? std::max(p->svd_cutoff, kCutoffMixed) : p->svd_cutoff;
   a.stop_tan = a.mixed ? kStopTanMixed : kStopTanFp64;
+  a.skip_tol = a.mixed ? kSkipMixed : kSkipFp64;
+  a.per_gate = (p->flags & TEPAI_PER_GATE) ? 1u : 0u;
   a.log_g1_step = t.log_step;
   a.l_eff = L;
   a.n = p->n_qubits;
@@ -650,51 +732,24 @@ tepai_status tepai_run(tepai_handle* h, const tepai_problem* p, uint32_t batch, 
   while (B > 1 && per1 + per * (B - 1) > free_b / 2) B /= 2;
   size_t ws_bytes = 0;
   if ((st = tepai_workspace_size(h, p, (uint32_t)B, &ws_bytes)) != TEPAI_OK) return st;
+  DeviceBuffers bufs;
   void* ws = nullptr;
   double *d_v = nullptr, *d_w = nullptr, *d_m = nullptr, *d_se = nullptr;
-  TEPAI_HIP(h, hipMalloc(&ws, ws_bytes));
-  TEPAI_HIP(h, hipMalloc(&d_v, sizeof(double) * ns * p->n_obs));
-  TEPAI_HIP(h, hipMalloc(&d_w, sizeof(double) * ns));
-  TEPAI_HIP(h, hipMalloc(&d_m, sizeof(double) * p->n_obs));
-  TEPAI_HIP(h, hipMalloc(&d_se, sizeof(double) * p->n_obs));
-  std::vector<tepai_sample_stats> sbuf;
-  for (uint64_t first = 0; first < ns && st == TEPAI_OK; first += B) {
-    const uint32_t cnt = (uint32_t)std::min<uint64_t>(B, ns - first);
-    tepai_batch* b = nullptr;
-    st = tepai_batch_create(h, p, first, cnt, ws, ws_bytes, nullptr, &b);
-    if (st != TEPAI_OK) break;
-    // launches of at most 16 Trotter steps keep single kernels short
-    for (uint32_t done = 0; done < p->trotter_steps && st == TEPAI_OK;) {
-      const uint32_t step = std::min<uint32_t>(16, p->trotter_steps - done);
-      st = tepai_batch_evolve(b, step);
-      done += step;
-    }
-    if (st == TEPAI_OK) st = tepai_batch_observe(b, d_v + first * p->n_obs, d_w + first);
-    if (st == TEPAI_OK && stats) st = tepai_batch_stats(b, stats + first);
-    if (st == TEPAI_OK) {
-      hipError_t e = hipStreamSynchronize(nullptr);
-      if (e != hipSuccess) st = fail(h, TEPAI_EDEVICE, std::string("batch: ") + hipGetErrorString(e));
-    }
-    tepai_batch_destroy(b);
-  }
-  if (st == TEPAI_OK) st = tepai_reduce(h, ns, p->n_obs, d_v, d_w, d_m, d_se, nullptr);
-  if (st == TEPAI_OK) {
-    hipError_t e = hipMemcpy(mean, d_m, sizeof(double) * p->n_obs, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(std_err, d_se, sizeof(double) * p->n_obs, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(weights, d_w, sizeof(double) * ns, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && values) e = hipMemcpy(values, d_v, sizeof(double) * ns * p->n_obs, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) st = fail(h, TEPAI_EDEVICE, std::string("copy-out: ") + hipGetErrorString(e));
-  }
-  (void)hipFree(ws);
-  (void)hipFree(d_v);
-  (void)hipFree(d_w);
-  (void)hipFree(d_m);
-  (void)hipFree(d_se);
-  if (st == TEPAI_OK) {
-    for (uint32_t o = 0; o < p->n_obs; ++o)
-      if (!std::isfinite(mean[o])) return fail(h, TEPAI_ENUMERIC, "non-finite estimate");
-  }
-  return st;
+  TEPAI_HIP(h, bufs.alloc(&ws, ws_bytes));
+  TEPAI_HIP(h, bufs.alloc(&d_v, sizeof(double) * ns * p->n_obs));
+  TEPAI_HIP(h, bufs.alloc(&d_w, sizeof(double) * ns));
+  TEPAI_HIP(h, bufs.alloc(&d_m, sizeof(double) * p->n_obs));
+  TEPAI_HIP(h, bufs.alloc(&d_se, sizeof(double) * p->n_obs));
+  std::vector<tepai_sample_stats> sbuf(stats ? 0 : ns);
+  tepai_sample_stats* sout = stats ? stats : sbuf.data();
+  st = run_batches(h, p, (uint32_t)B, ws, ws_bytes, nullptr, d_v, d_w, d_m, d_se, sout);
+  if (st != TEPAI_OK) return st;
+  hipError_t e = hipMemcpy(mean, d_m, sizeof(double) * p->n_obs, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(std_err, d_se, sizeof(double) * p->n_obs, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(weights, d_w, sizeof(double) * ns, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && values) e = hipMemcpy(values, d_v, sizeof(double) * ns * p->n_obs, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(h, TEPAI_EDEVICE, std::string("copy-out: ") + hipGetErrorString(e));
+  return numeric_status(h, p, sout, mean);
 }
 
 }  // extern "C"

@@ -164,6 +164,11 @@ __device__ __forceinline__ void atomicMax_double(double* a, double v) {
 }
 
 
+// Ordering key of a squared column norm: a NaN sorts below every number, so
+// the rank computations below always produce a permutation (a non-finite
+// matrix must still leave every index in range).
+__device__ __forceinline__ double norm_key(double v) { return v == v ? v : -1.0; }
+
 // 1/sqrt(x) and 1/x from the hardware estimates refined by two Newton steps
 // (each step squares the relative error) for the rotation parameters.
 __device__ __forceinline__ double rsq_nr(double x) {
@@ -203,16 +208,30 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
+// Workgroup barrier for data that waves hand to each other through global
+// memory (site tensors, the scratch matrices).  The compiler's
+// workgroup-scope fence around __syncthreads waits only for LDS operations
+// (outstanding vector memory operations are not awaited when a work-group
+// runs on one CU), so a wave's global store, or a global load still in
+// flight, could race with another wave's access after the barrier: measured
+// as occasional stale columns (errors of the order of the last Jacobi sweep's
+// rotations) in the factorisations.  Waiting for every vector memory
+// operation of the wave first orders those hand-offs.
+__device__ __forceinline__ void sync_block() {
+  __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+}
+
 // Fixed-order block sum (deterministic); all threads get the result.
 __device__ double block_sum(double v, double* red) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   v = wave_sum(v);
-  __syncthreads();
+  sync_block();
   if (lane == 0) red[wv] = v;
-  __syncthreads();
+  sync_block();
   double t = 0.0;
   for (int w = 0; w < NW; ++w) t += red[w];
-  __syncthreads();
+  sync_block();
   return t;
 }
 
@@ -255,6 +274,7 @@ struct Shared {
   double sum_chi3, flops, discarded, max_disc, min_gap;
   int n_c;
   uint32_t max_bond;
+  uint32_t sflags;       // TEPAI_SAMPLE_* bits
 };
 
 struct Slot {
@@ -264,10 +284,12 @@ struct Slot {
   z2* P;      // scratch: projections
   z2* Jl;     // LDS staging block of the Jacobi sweeps
   uint64_t ss;     // site stride
-  double stop;       // Jacobi stops after a sweep whose |tan| <= stop
+  double stop;       // Jacobi stops after a sweep whose pair cosines were all <= stop
+  double skip;       // Jacobi skips a pair with |x^H y| <= skip sqrt(R) |x||y|
   double cutoff;
   uint32_t chi;
   uint32_t n;
+  uint32_t per_gate;  // every two-qubit gate its own update (no run fusion)
 };
 
 template <typename TS>
@@ -374,7 +396,8 @@ constexpr double kNormRecompute = 0.25;
 // LDS and stay zero), so the element loop is straight-line code that the
 // compiler can interleave.  Rows that are inactive or
 // already orthogonal to tolerance leave both columns untouched.  Returns
-// |t| = |tan| of the rotation angle, or -1 when this row did not rotate.
+// the cosine |x^H y| / (|x||y|) of the pair before the rotation, or -1 when
+// this row did not rotate.
 template <int E>
 __device__ __forceinline__ double rotate_rows(z2 (&x)[E], double& al, lz2* y, ld* yn, int l16,
                                               bool active, double tiny, double tol2) {
@@ -395,7 +418,7 @@ __device__ __forceinline__ double rotate_rows(z2 (&x)[E], double& al, lz2* y, ld
   double tabs = -1.0;
   if (rot) {
     const Rot r = rot_params(al, be, gr, gi, g2);
-    tabs = fabs(r.t);
+    tabs = sqrt(g2 / (al * be));
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       rot_apply(r, x[e], yv[e]);
@@ -446,7 +469,7 @@ __device__ __forceinline__ double rotate_split(lz2* xp, lz2* yq, ld* pn, ld* qn,
   double tabs = -1.0;
   if (rot) {
     const Rot r = rot_params(al, be, gr, gi, g2);
-    tabs = fabs(r.t);
+    tabs = sqrt(g2 / (al * be));
 #pragma unroll
     for (int e = 0; e < EG; ++e) {
       rot_apply(r, xv[e], yv[e]);
@@ -520,7 +543,8 @@ __device__ __forceinline__ double row_norm2(const z2 (&x)[E]) {
 // staging block (JB columns).  Returns the number of sweeps, or -1 when the
 // sweep cap was reached.
 template <int RPL>
-__device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_, double stop) {
+__device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_, double stop,
+                                   double skip) {
   using K = JCfg<RPL>;
   constexpr int E = K::E, JB = K::JB, LR = K::LR;
   gz2* W = (gz2*)W_;
@@ -536,22 +560,22 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_, do
     const double a = row_norm2<E>(x);
     if (l16 == 0) sh.sig2[j] = a;
   }
-  __syncthreads();
+  sync_block();
   double fro2 = 0.0;
   for (int j = 0; j < C; ++j) fro2 += sh.sig2[j];
   const double tiny = 1e-32 * fro2;     // sigma_j^2 below this is numerically zero
-  const double tol = 1e-15 * sqrt((double)R);
+  const double tol = skip * sqrt((double)R);
   const double tol2 = tol * tol;
   const int nb = (C + JB - 1) / JB;
 #pragma unroll 1
   for (int sweep = 1; sweep <= kMaxSweeps; ++sweep) {
     // order columns by decreasing norm (ties by index): de Rijk's ordering
     for (int j = threadIdx.x; j < C; j += NT) {
-      const double v = sh.sig2[j];
+      const double v = norm_key(sh.sig2[j]);
       int rank = 0;
 #pragma unroll 4
       for (int i = 0; i < C; ++i) {
-        const double u = sh.sig2[i];
+        const double u = norm_key(sh.sig2[i]);
         rank += (u > v) || (u == v && i < j);
       }
       sh.order[rank] = (uint16_t)j;
@@ -560,8 +584,8 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_, do
       sh.flag = 0;
       sh.tmax = 0.0;
     }
-    __syncthreads();
-    double tmx = -1.0;     // largest |tan| of the rotations this thread's row applied
+    sync_block();
+    double tmx = -1.0;     // largest cosine of the pairs this thread's row rotated
 #pragma unroll 1
     for (int I = 0; I < nb; ++I) {
       const int pi = I * JB + row;                       // position of this row's column
@@ -590,7 +614,7 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_, do
           const double b = row_norm2<E>(y);
           if (l16 == 0) jn[row] = b;
         }
-        __syncthreads();
+        sync_block();
         // Cross pairs in 4 x 4 tiles: wave w (rows 4w..4w+3) owns I-tile w and
         // visits the J-tiles (w + R) mod NTILE; inside a tile its four rows
         // meet the four J columns in four wave-local rounds (LDS is in order
@@ -610,14 +634,14 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_, do
               __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
             }
           }
-          __syncthreads();
+          sync_block();
         }
         if (row < JB && J * JB + row < C) {
           z2 y[E];
           row_load_l<E>(y, Jl + row * LR, l16);
           row_store_g<E>(y, W + (uint64_t)sh.order[J * JB + row] * R, R, l16);
         }
-        __syncthreads();
+        sync_block();
       }
       // pairs inside block I, in LDS (round-robin over the block's columns,
       // rounded up to an even count); each of the pairs of a round is shared
@@ -626,7 +650,7 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_, do
         row_store_l<E>(xi, Jl + row * LR, l16);
         if (l16 == 0) jn[row] = al;
       }
-      __syncthreads();
+      sync_block();
       {
         constexpr int G = NROWS / (JB / 2), EG = E / G;
         const int k = row / G, h = row - k * G;
@@ -640,7 +664,7 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_, do
           const bool act = pk && I * JB + q < C;
           tmx = fmax(tmx, rotate_split<EG, G>(Jl + p * LR, Jl + q * LR, jn + p, jn + q, h * EG,
                                                l16, h == 0, act, tiny, tol2));
-          __syncthreads();
+          sync_block();
         }
       }
       // write block I back and record its final column norms for the next order
@@ -651,22 +675,24 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_, do
         const double a = row_norm2<E>(x);
         if (l16 == 0) sh.sig2[ci] = a;
       }
-      __syncthreads();
+      sync_block();
     }
-    // Stop when no pair rotated, or when every rotation of this sweep turned
-    // by |tan| <= stop: the columns then moved by at most `stop` of their
-    // partners, so the non-orthogonality left behind is ~stop^2 (1e-16 at the
-    // FP64 path's 1e-8, where a further sweep would find nothing above the
-    // tolerance).
+    // Stop when no pair rotated, or when every pair this sweep rotated had a
+    // cosine |x^H y| / (|x||y|) <= stop: the sweep then leaves a
+    // non-orthogonality of ~stop^2 (1e-16 at the FP64 path's 1e-8, where a
+    // further sweep would find nothing above the tolerance).  The test is on
+    // the cosine, not on the rotation's tangent, which is smaller by the
+    // ratio of the two norms: a column far smaller than its partner can meet
+    // a tangent bound while still far from orthogonal to it.
     tmx = wave_max(tmx);
     if ((threadIdx.x & 63) == 0 && tmx >= 0.0) {
       sh.flag = 1;
       atomicMax_double(&sh.tmax, tmx);
     }
-    __syncthreads();
+    sync_block();
     const int rotated = sh.flag;
     const double tm = sh.tmax;
-    __syncthreads();
+    sync_block();
     if (!rotated || tm <= stop) return sweep;
   }
   return -1;
@@ -725,7 +751,10 @@ __device__ __forceinline__ void zgemm(int M, int N, int K, const FA& fa, const F
         for (int a = 0; a < 2; ++a)
 #pragma unroll
           for (int b = 0; b < 2; ++b) {
-            cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[s][a].y, bv[s][b].y, cr[a][b], 0, 0, 0);
+            // - Ai Bi with the instruction's own negation of source A (the
+            // NEG[0] bit in the BLGP field of an FP64 MFMA), so no VALU
+            // writes a negated copy into registers an MFMA in flight reads
+            cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][a].y, bv[s][b].y, cr[a][b], 0, 0, 1);
             ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][a].y, bv[s][b].x, ci[a][b], 0, 0, 0);
           }
       }
@@ -875,13 +904,13 @@ __device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_, z
   exact_norms(0);
   for (int i = threadIdx.x; i < nc; i += NT) sh.piv[i] = (uint16_t)i;
   if (threadIdx.x == 0) sh.qr_done = 0;
-  __syncthreads();
+  sync_block();
 
 #pragma unroll 1
   for (int j0 = 0; j0 < m;) {
     const int kmax = (m - j0) < nbmax ? (m - j0) : nbmax;
     if (threadIdx.x == 0) sh.qr_mark = 0;
-    __syncthreads();
+    sync_block();
     int kb = 0;
 #pragma unroll 1
     for (int k = 0; k < kmax; ++k) {
@@ -911,7 +940,7 @@ __device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_, z
           if (!(best > 0.0) && k == 0) sh.qr_done = 1;   // exact norms: the rest is zero
         }
       }
-      __syncthreads();
+      sync_block();
       const int p = sh.qr_p;
       if (!(sh.qr_v > 0.0)) break;     // (downdated norms: re-check after the update)
       if (p != j) {
@@ -940,7 +969,7 @@ __device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_, z
         }
       }
       if (threadIdx.x < k) sh.qr_w[threadIdx.x] = Wb[(uint64_t)threadIdx.x * nc + j];
-      __syncthreads();
+      sync_block();
       // the pivot column brought up to date, and its reflector (wave 0)
       if (wv == 0) {
         const gz2* col = Z + (uint64_t)j * nr;
@@ -977,7 +1006,7 @@ __device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_, z
           sh.qr_k = xn > 0.0 ? 1.0 / (xn * (xn + aa)) : 0.0;
         }
       }
-      __syncthreads();
+      sync_block();
       // t_i = u_k^H u_i for the panel's earlier reflectors
       if (row < k) {
         double tr = 0.0, ti = 0.0;
@@ -990,7 +1019,7 @@ __device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_, z
         ti = row16_sum(ti);
         if (l16 == 0) sh.qr_t[row] = cmk(tr, ti);
       }
-      __syncthreads();
+      sync_block();
       // trailing columns: W_k(c), the new row j of R, downdated norms (read-only pass)
       {
         const double kap = sh.qr_k;
@@ -1077,7 +1106,7 @@ __device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_, z
           }
         }
       }
-      __syncthreads();
+      sync_block();
       ++kb;
       if (sh.qr_mark) break;
     }
@@ -1091,10 +1120,10 @@ __device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_, z
               const z2 o = *at;
               *at = cmk(o.x - v.x, o.y - v.y);
             });
-      __syncthreads();
+      sync_block();
     }
     if (r0 < nc) exact_norms(r0 < nr ? r0 : nr);
-    __syncthreads();
+    sync_block();
     j0 = r0;
     if (sh.qr_done) break;
   }
@@ -1103,11 +1132,11 @@ __device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_, z
 // Jacobi with the smallest row class that holds R rows (the element loops
 // run over all E = 4 RPL elements of a lane, so a smaller class saves work).
 template <int RPL>
-__device__ int jacobi_fit(z2* X, int R, int C, Shared& sh, z2* Jl, double stop) {
+__device__ int jacobi_fit(z2* X, int R, int C, Shared& sh, z2* Jl, double stop, double skip) {
   if constexpr (RPL > 1) {
-    if (R <= 32 * RPL) return jacobi_fit<RPL / 2>(X, R, C, sh, Jl, stop);
+    if (R <= 32 * RPL) return jacobi_fit<RPL / 2>(X, R, C, sh, Jl, stop, skip);
   }
-  return jacobi<RPL>(X, R, C, sh, Jl, stop);
+  return jacobi<RPL>(X, R, C, sh, Jl, stop, skip);
 }
 
 // Left singular vectors of M (R x C, column-major in Y0): Z = M^H is
@@ -1120,7 +1149,7 @@ __device__ int jacobi_fit(z2* X, int R, int C, Shared& sh, z2* Jl, double stop) 
 // preconditioning of one-sided Jacobi).  Returns the sweeps (-1 at the cap).
 template <int RPL, bool MIX>
 __device__ int svd_cols(z2* W, const z2* Y0, z2* X, int R, int C, Shared& sh, z2* Jl,
-                         double stop) {
+                         double stop, double skip) {
   // the QR works on complex128 on both paths: its passes are bound by
   // instruction issue, and complex64 storage costs more in conversions than
   // it saves in bytes
@@ -1130,20 +1159,20 @@ __device__ int svd_cols(z2* W, const z2* Y0, z2* X, int R, int C, Shared& sh, z2
     const int c = idx / R, r = idx - c * R;
     Z[(uint64_t)r * C + c] = fromz<TZ>(cconj(Y0[idx]));
   }
-  __syncthreads();
+  sync_block();
   qrcp<RPL>(W, C, R, sh, Jl, X);      // X holds the QR's panel coefficients until it is built
   const int m = R < C ? R : C;
   for (int idx = threadIdx.x; idx < R * m; idx += NT) {
     const int jj = idx / R, r = idx - jj * R;
     X[idx] = jj <= r ? cconj(toz(Z[(uint64_t)r * C + jj])) : cmk(0.0, 0.0);
   }
-  __syncthreads();
-  const int sweeps = jacobi_fit<RPL>(X, R, m, sh, Jl, stop);
+  sync_block();
+  const int sweeps = jacobi_fit<RPL>(X, R, m, sh, Jl, stop, skip);
   for (int idx = threadIdx.x; idx < R * m; idx += NT) {
     const int jj = idx / R, r = idx - jj * R;
     W[(uint64_t)jj * R + sh.piv[r]] = X[idx];
   }
-  __syncthreads();
+  sync_block();
   return sweeps;
 }
 
@@ -1158,9 +1187,9 @@ struct Factor {
 // the column of W holding the j-th largest sigma.
 template <int RPL, bool MIX>
 __device__ Factor factorise(z2* W, const z2* Y0, z2* X, int R, int C_, int cap, double cutoff,
-                            bool record, Shared& sh, z2* Jl, double stop) {
+                            bool record, Shared& sh, z2* Jl, double stop, double skip) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int sweeps = svd_cols<RPL, MIX>(W, Y0, X, R, C_, sh, Jl, stop);
+  const int sweeps = svd_cols<RPL, MIX>(W, Y0, X, R, C_, sh, Jl, stop, skip);
   const int C = R < C_ ? R : C_;     // columns of W from here on
   for (int j = wv; j < C; j += NW) {
     const z2* w = W + (uint64_t)j * R;
@@ -1169,17 +1198,17 @@ __device__ Factor factorise(z2* W, const z2* Y0, z2* X, int R, int C_, int cap, 
     a = wave_sum(a);
     if (lane == 0) sh.sig2[j] = a;
   }
-  __syncthreads();
+  sync_block();
   for (int j = threadIdx.x; j < C; j += NT) {
-    const double v = sh.sig2[j];
+    const double v = norm_key(sh.sig2[j]);
     int rank = 0;
     for (int i = 0; i < C; ++i) {
-      const double u = sh.sig2[i];
+      const double u = norm_key(sh.sig2[i]);
       rank += (u > v) || (u == v && i < j);
     }
     sh.perm[rank] = (uint16_t)j;
   }
-  __syncthreads();
+  sync_block();
   const double s0 = sh.sig2[sh.perm[0]];
   const double thr = cutoff * cutoff * s0;
   int r = 0;
@@ -1195,20 +1224,30 @@ __device__ Factor factorise(z2* W, const z2* Y0, z2* X, int R, int C_, int cap, 
   for (int j = 0; j < k; ++j) kept += sh.sig2[sh.perm[j]];
   if (threadIdx.x == 0) {
     sh.sweeps += (sweeps < 0 ? kMaxSweeps : sweeps);
-    if (sweeps < 0) sh.nonconv += 1;
+    if (sweeps < 0) {
+      sh.nonconv += 1;
+      sh.sflags |= TEPAI_SAMPLE_NONCONVERGED;
+    }
+    if (!isfinite(tot) || !(kept > 0.0)) sh.sflags |= TEPAI_SAMPLE_NONFINITE;
     if (record) {
       const double disc = tot > 0.0 ? (tot - kept) / tot : 0.0;
       sh.discarded += disc;
       if (disc > sh.max_disc) sh.max_disc = disc;
       if (k < r) {   // a cut made by the bond cap
-        const double sk = sh.sig2[sh.perm[k]];
-        const double gap = (sqrt(sh.sig2[sh.perm[k - 1]]) - sqrt(sk)) / sqrt(s0);
+        // near tie: an SVD with backward error eps = u sqrt(R C) (relative
+        // to sigma_0) fixes the straddling pair to the angle
+        // th = min(1, eps / gap), which moves a unit-norm observable by at
+        // most 2 sqrt(2) th sigma_{k-1} / |sigma_kept|; doubled for two SVDs
+        const double skm = sqrt(sh.sig2[sh.perm[k - 1]]);
+        const double gap = (skm - sqrt(sh.sig2[sh.perm[k]])) / sqrt(s0);
         if (gap < sh.min_gap) sh.min_gap = gap;
-        if (gap <= 1e-10) sh.ties += 1;
+        const double eps = 0x1p-53 * sqrt((double)R * (double)C_);
+        const double th = gap <= eps ? 1.0 : eps / gap;
+        if (4.0 * sqrt(2.0) * th * skm / sqrt(kept) > 1e-10) sh.ties += 1;
       }
     }
   }
-  __syncthreads();
+  sync_block();
   Factor fr;
   fr.k = k;
   fr.scale = 1.0 / sqrt(kept);
@@ -1227,7 +1266,7 @@ __device__ void project(const z2* W, const z2* Y0, z2* P, int R, int C, int k,
         [&](int j, int r) { return cconj((z2)w[(uint64_t)sh.perm[j] * R + r]); },
         [&](int r, int col) { return (z2)y[(uint64_t)col * R + r]; },
         [&](int j, int col, z2 v) { out[(uint64_t)j * C + col] = cscale(v, rsq_nr(sh.sig2[sh.perm[j]])); });
-  __syncthreads();
+  sync_block();
 }
 
 // -------------------------------------------------------- MPS operations
@@ -1249,7 +1288,7 @@ __device__ void apply_local(const Slot& S, int k, const z2 U[4], Shared& sh) {
     *x0 = fromz<TS>(o0);
     *x1 = fromz<TS>(o1);
   }
-  __syncthreads();
+  sync_block();
 }
 
 // Move the centre from site c to c+1 (SVD of A_c as a (2 cl) x cr matrix).
@@ -1264,8 +1303,8 @@ __device__ void shift_right(const Slot& S, int c, double cutoff, Shared& sh) {
     const int row = idx / C, col = idx - row * C;
     S.Y0[(uint64_t)col * R + row] = toz(A[idx]);
   }
-  __syncthreads();
-  const Factor f = factorise<RPL, MIX>(S.W, S.Y0, S.P, R, C, C, cutoff, false, sh, S.Jl, S.stop);
+  sync_block();
+  const Factor f = factorise<RPL, MIX>(S.W, S.Y0, S.P, R, C, C, cutoff, false, sh, S.Jl, S.stop, S.skip);
   const int k = f.k;
   project<MIX>(S.W, S.Y0, S.P, R, C, k, sh);
   for (int idx = threadIdx.x; idx < R * k; idx += NT) {
@@ -1274,7 +1313,7 @@ __device__ void shift_right(const Slot& S, int c, double cutoff, Shared& sh) {
     A[idx] = fromz<TS>(cscale(S.W[(uint64_t)pj * R + row], 1.0 / sqrt(sh.sig2[pj])));
   }
   // B' = P . B  (k x cr) . (cr x 2 cr2) into W, then back
-  __syncthreads();
+  sync_block();
   const int nb = 2 * cr2;
   {
     const gz2* pp = (const gz2*)S.P;
@@ -1284,14 +1323,14 @@ __device__ void shift_right(const Slot& S, int c, double cutoff, Shared& sh) {
           [&](int b, int col) { return toz((TS)bb[(uint64_t)b * nb + col]); },
           [&](int j, int col, z2 v) { ww[(uint64_t)j * nb + col] = v; });
   }
-  __syncthreads();
+  sync_block();
   for (int idx = threadIdx.x; idx < k * nb; idx += NT) B[idx] = fromz<TS>(S.W[idx]);
   if (threadIdx.x == 0) {
     sh.bond[c + 1] = (uint16_t)k;
     sh.centre = c + 1;
     sh.shifts += 1;
   }
-  __syncthreads();
+  sync_block();
 }
 
 // Move the centre from site c to c-1 (SVD of A_c as a cl x (2 cr) matrix).
@@ -1305,8 +1344,8 @@ __device__ void shift_left(const Slot& S, int c, double cutoff, Shared& sh) {
   for (int idx = threadIdx.x; idx < R * C; idx += NT) {
     S.Y0[idx] = cconj(toz(A[idx]));      // Y = A^H, same memory order
   }
-  __syncthreads();
-  const Factor f = factorise<RPL, MIX>(S.W, S.Y0, S.P, R, C, C, cutoff, false, sh, S.Jl, S.stop);
+  sync_block();
+  const Factor f = factorise<RPL, MIX>(S.W, S.Y0, S.P, R, C, C, cutoff, false, sh, S.Jl, S.stop, S.skip);
   const int k = f.k;
   project<MIX>(S.W, S.Y0, S.P, R, C, k, sh);
   for (int idx = threadIdx.x; idx < k * R; idx += NT) {
@@ -1314,7 +1353,7 @@ __device__ void shift_left(const Slot& S, int c, double cutoff, Shared& sh) {
     const int pj = sh.perm[j];
     A[idx] = fromz<TS>(cconj(cscale(S.W[(uint64_t)pj * R + col], 1.0 / sqrt(sh.sig2[pj]))));
   }
-  __syncthreads();
+  sync_block();
   // B' [x, s, j] = sum_a B[x, s, a] conj(P[j, a])
   const int nrow = 2 * cl0;
   {
@@ -1325,14 +1364,14 @@ __device__ void shift_left(const Slot& S, int c, double cutoff, Shared& sh) {
           [&](int a, int j) { return cconj((z2)pp[(uint64_t)j * C + a]); },
           [&](int xs, int j, z2 v) { ww[(uint64_t)xs * k + j] = v; });
   }
-  __syncthreads();
+  sync_block();
   for (int idx = threadIdx.x; idx < nrow * k; idx += NT) B[idx] = fromz<TS>(S.W[idx]);
   if (threadIdx.x == 0) {
     sh.bond[c] = (uint16_t)k;
     sh.centre = c - 1;
     sh.shifts += 1;
   }
-  __syncthreads();
+  sync_block();
 }
 
 template <int RPL, bool MIX>
@@ -1363,7 +1402,7 @@ __device__ void two_site(const Slot& S, int i, bool right, bool is_swap, Shared&
           [&](int b, int j) { return toz((TS)bb[(uint64_t)b * N + j]); },
           [&](int i, int j, z2 v) { ww[(uint64_t)i * N + j] = v; });
   }
-  __syncthreads();
+  sync_block();
   for (int idx = threadIdx.x; idx < cl * cr; idx += NT) {
     const int a = idx / cr, c = idx - a * cr;
     z2 tv[4];
@@ -1389,8 +1428,8 @@ __device__ void two_site(const Slot& S, int i, bool right, bool is_swap, Shared&
       }
     }
   }
-  __syncthreads();
-  const Factor f = factorise<RPL, MIX>(S.W, S.Y0, S.P, R, C, (int)S.chi, S.cutoff, true, sh, S.Jl, S.stop);
+  sync_block();
+  const Factor f = factorise<RPL, MIX>(S.W, S.Y0, S.P, R, C, (int)S.chi, S.cutoff, true, sh, S.Jl, S.stop, S.skip);
   const int k = f.k;
   project<MIX>(S.W, S.Y0, S.P, R, C, k, sh);
   if (right) {
@@ -1413,7 +1452,7 @@ __device__ void two_site(const Slot& S, int i, bool right, bool is_swap, Shared&
       A[idx] = fromz<TS>(cconj(cscale(S.P[(uint64_t)j * C + row], f.scale)));
     }
   }
-  __syncthreads();
+  sync_block();
   if (threadIdx.x == 0) {
     sh.bond[i + 1] = (uint16_t)k;
     sh.centre = right ? i + 1 : i;
@@ -1423,7 +1462,7 @@ __device__ void two_site(const Slot& S, int i, bool right, bool is_swap, Shared&
     sh.flops += 8.0 * M * cm * N + svd_flops(M, N);
     if ((uint32_t)k > sh.max_bond) sh.max_bond = k;
   }
-  __syncthreads();
+  sync_block();
 }
 
 template <int RPL, bool MIX>
@@ -1434,7 +1473,7 @@ __device__ void swap_sites(const Slot& S, int i, bool right, Shared& sh) {
     const int sw = ((c & 1) << 1) | (c >> 1);
     sh.G[threadIdx.x] = cmk(r == sw ? 1.0 : 0.0, 0.0);
   }
-  __syncthreads();
+  sync_block();
   two_site<RPL, MIX>(S, i, right, true, sh);
   if (threadIdx.x == 0) {
     const int a = sh.qubit_at[i], b = sh.qubit_at[i + 1];
@@ -1443,7 +1482,7 @@ __device__ void swap_sites(const Slot& S, int i, bool right, Shared& sh) {
     sh.site_of[a] = (uint16_t)(i + 1);
     sh.site_of[b] = (uint16_t)i;
   }
-  __syncthreads();
+  sync_block();
 }
 
 // Apply the pending same-pair run (if any) and clear it.
@@ -1488,7 +1527,7 @@ __device__ void flush(const Slot& S, Shared& sh) {
       const int cc = ia < ib ? c : ((c & 1) << 1 | (c >> 1));
       sh.G[threadIdx.x] = sh.pM[rr * 4 + cc];
     }
-    __syncthreads();
+    sync_block();
     two_site<RPL, MIX>(S, at, true, false, sh);
     if (carry && threadIdx.x == 0) {
       const int a = sh.qubit_at[at], b = sh.qubit_at[at + 1];
@@ -1497,10 +1536,10 @@ __device__ void flush(const Slot& S, Shared& sh) {
       sh.site_of[a] = (uint16_t)(at + 1);
       sh.site_of[b] = (uint16_t)at;
     }
-    __syncthreads();
+    sync_block();
   }
   if (threadIdx.x == 0) sh.p_active = 0;
-  __syncthreads();
+  sync_block();
 }
 
 // Process one sampled non-identity gate (setting 1 = B, 2 = C) of row r.
@@ -1583,7 +1622,8 @@ __device__ void process_gate(const Slot& S, const DevRow& row, int setting, int 
       sh.pPhase = cmul(sh.pPhase, cmk(0.0, -1.0));
     }
   }
-  __syncthreads();
+  sync_block();
+  if (S.per_gate) flush<RPL, MIX>(S, sh);   // the run holds this one gate
 }
 
 __device__ void load_state(const EngineArgs& a, int slot, Shared& sh) {
@@ -1610,9 +1650,10 @@ __device__ void load_state(const EngineArgs& a, int slot, Shared& sh) {
     sh.min_gap = st->min_gap;
     sh.max_bond = st->max_bond;
     sh.n_c = st->sign < 0 ? 1 : 0;
+    sh.sflags = st->flags;
     sh.p_active = 0;
   }
-  __syncthreads();
+  sync_block();
 }
 
 __device__ void store_state(const EngineArgs& a, int slot, Shared& sh, uint32_t layer) {
@@ -1635,6 +1676,7 @@ __device__ void store_state(const EngineArgs& a, int slot, Shared& sh, uint32_t 
     st->min_gap = sh.min_gap;
     st->max_bond = sh.max_bond;
     st->sign = (sh.n_c & 1) ? -1 : 1;
+    st->flags = sh.sflags;
     st->layer = layer;
   }
 }
@@ -1651,8 +1693,10 @@ __device__ Slot make_slot(const EngineArgs& a, int slot, z2* Jl) {
   S.P = S.W + q;
   S.cutoff = a.cutoff;
   S.stop = a.stop_tan;
+  S.skip = a.skip_tol;
   S.chi = a.states[slot].chi_cap;
   S.n = a.n;
+  S.per_gate = a.per_gate;
   return S;
 }
 
@@ -1726,14 +1770,14 @@ __global__ __launch_bounds__(NT) void evolve_kernel(EngineArgs a, uint32_t n_lay
       sh.n_gates += (uint64_t)tz;
       sh.n_c += (int)tc;
     }
-    __syncthreads();
+    sync_block();
     for (uint32_t r = 0; r < L; ++r) {
       const int c = sh.choice[r];
       if (c == 0) continue;
       process_gate<RPL, MIX>(S, a.rows[r], c, (int)layer, sh);
     }
     flush<RPL, MIX>(S, sh);     // runs end at Trotter-step boundaries
-    __syncthreads();  // every thread is done reading this step's settings
+    sync_block();  // every thread is done reading this step's settings
   }
   store_state(a, slot, sh, layer0 + n_layers);
 }
@@ -1783,7 +1827,7 @@ __device__ void env_left(const TSite<MIX>* A_, int kl, int kr, const z2* E_, z2*
   zgemm_p<MIX>(kl, n2, kl, [&](int i, int k) { return (z2)E[(uint64_t)i * kl + k]; },
                [&](int k, int j) { return toz((TS)A[(uint64_t)k * n2 + j]); },
                [&](int i, int j, z2 v) { F[(uint64_t)i * n2 + j] = v; });
-  __syncthreads();
+  sync_block();
   if (!O.id) {
     for (int idx = threadIdx.x; idx < kl * kr; idx += NT) {
       const int a = idx / kr, b = idx - a * kr;
@@ -1796,13 +1840,13 @@ __device__ void env_left(const TSite<MIX>* A_, int kl, int kr, const z2* E_, z2*
       F[(uint64_t)a * n2 + b] = g0;
       F[(uint64_t)a * n2 + kr + b] = g1;
     }
-    __syncthreads();
+    sync_block();
   }
   // rows r = (a', s') of A and F, kr columns each
   zgemm_p<MIX>(kr, kr, 2 * kl, [&](int bp, int r) { return cconj(toz((TS)A[(uint64_t)r * kr + bp])); },
                [&](int r, int b) { return (z2)F[(uint64_t)r * kr + b]; },
                [&](int bp, int b, z2 v) { Eo[(uint64_t)bp * kr + b] = v; });
-  __syncthreads();
+  sync_block();
 }
 
 // Right environment through site A: R'[a][a'] = sum A[a,s,b] R[b][b'] conj(A[a',s,b'])
@@ -1817,22 +1861,22 @@ __device__ void env_right(const TSite<MIX>* A_, int kl, int kr, const z2* R_, z2
   zgemm_p<MIX>(2 * kl, kr, kr, [&](int r, int b) { return toz((TS)A[(uint64_t)r * kr + b]); },
                [&](int b, int bp) { return (z2)R[(uint64_t)b * kr + bp]; },
                [&](int r, int bp, z2 v) { F[(uint64_t)r * kr + bp] = v; });
-  __syncthreads();
+  sync_block();
   const int n2 = 2 * kr;
   zgemm_p<MIX>(kl, kl, n2, [&](int a, int j) { return (z2)F[(uint64_t)a * n2 + j]; },
                [&](int j, int ap) { return cconj(toz((TS)A[(uint64_t)ap * n2 + j])); },
                [&](int a, int ap, z2 v) { Ro[(uint64_t)a * kl + ap] = v; });
-  __syncthreads();
+  sync_block();
 }
 
 __device__ void set_identity(z2* M, int d) {
   for (int idx = threadIdx.x; idx < d * d; idx += NT) M[idx] = cmk((idx / d) == (idx % d) ? 1.0 : 0.0, 0.0);
-  __syncthreads();
+  sync_block();
 }
 
 __device__ void copy_mat(z2* dst, const z2* src, int len) {
   for (int idx = threadIdx.x; idx < len; idx += NT) dst[idx] = src[idx];
-  __syncthreads();
+  sync_block();
 }
 
 // Re sum_{b,b'} E[b'][b] R[b][b'] (R = null: the identity), all threads get it.
@@ -1917,7 +1961,7 @@ __global__ __launch_bounds__(NT) void observe_kernel(EngineArgs a, double* value
   };
   auto add = [&](const DevString& str, double v) {
     if (threadIdx.x == 0) acc_obs[str.observable] += str.coeff * v / norm2;
-    __syncthreads();
+    sync_block();
   };
 
   // strings that start at or right of the centre: left-to-right sweep
@@ -1953,7 +1997,7 @@ __global__ __launch_bounds__(NT) void observe_kernel(EngineArgs a, double* value
       if (l == k - 1) add(str, string_value(str, f, l, nullptr, env));
     }
   }
-  __syncthreads();
+  sync_block();
   const SampleState* st = a.states + slot;
   for (uint32_t o = threadIdx.x; o < a.n_obs; o += NT)
     values[(uint64_t)slot * a.n_obs + o] = acc_obs[o];
@@ -2016,23 +2060,24 @@ __global__ __launch_bounds__(NT) void sample_write_kernel(const DevRow* rows, ui
     uint8_t c = 0;
     if (g < n_draws) c = draw_setting(rows[g % L], seed, sample, g);
     scan[threadIdx.x] = c != 0;
-    __syncthreads();
+    sync_block();
     // inclusive Hillis-Steele scan over the block
     for (int off = 1; off < NT; off <<= 1) {
       const int v = threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
-      __syncthreads();
+      sync_block();
       scan[threadIdx.x] += v;
-      __syncthreads();
+      sync_block();
     }
     if (c != 0) words[base + scan[threadIdx.x] - 1] = (uint32_t)(g * 4 + c);
     base += scan[NT - 1];
-    __syncthreads();
+    sync_block();
   }
 }
 
 }  // namespace
 
 hipError_t launch_init(const EngineArgs& a, hipStream_t s) {
+  (void)hipGetLastError();   // an earlier call's error was reported by that call
   if (a.mixed)
     hipLaunchKernelGGL(init_kernel<true>, dim3(a.count), dim3(NT), 0, s, a);
   else
@@ -2057,6 +2102,7 @@ static void evolve_rpl(const EngineArgs& a, uint32_t n_layers, hipStream_t s) {
 }
 
 hipError_t launch_evolve(const EngineArgs& a, uint32_t n_layers, hipStream_t s) {
+  (void)hipGetLastError();
   if (a.mixed)
     evolve_rpl<true>(a, n_layers, s);
   else
@@ -2076,6 +2122,7 @@ static void observe_rpl(const EngineArgs& a, double* v, double* w, hipStream_t s
 
 hipError_t launch_observe(const EngineArgs& a, double* d_values, double* d_weights,
                           hipStream_t s) {
+  (void)hipGetLastError();
   if (a.mixed)
     observe_rpl<true>(a, d_values, d_weights, s);
   else
@@ -2085,6 +2132,7 @@ hipError_t launch_observe(const EngineArgs& a, double* d_values, double* d_weigh
 
 hipError_t launch_reduce(uint64_t count, uint32_t n_obs, const double* v, const double* w,
                          double* mean, double* se, hipStream_t s) {
+  (void)hipGetLastError();
   hipLaunchKernelGGL(reduce_kernel, dim3(n_obs), dim3(NT), 0, s, count, n_obs, v, w, mean, se);
   return hipGetLastError();
 }
@@ -2092,6 +2140,7 @@ hipError_t launch_reduce(uint64_t count, uint32_t n_obs, const double* v, const 
 hipError_t launch_sample_count(const DevRow* rows, uint32_t l_eff, uint64_t seed,
                                uint64_t first_sample, uint64_t count, uint64_t n_draws,
                                uint64_t* d_counts, int8_t* d_signs, hipStream_t s) {
+  (void)hipGetLastError();
   hipLaunchKernelGGL(sample_count_kernel, dim3((uint32_t)count), dim3(NT), 0, s, rows, l_eff,
                      seed, first_sample, n_draws, d_counts, d_signs);
   return hipGetLastError();
@@ -2100,6 +2149,7 @@ hipError_t launch_sample_count(const DevRow* rows, uint32_t l_eff, uint64_t seed
 hipError_t launch_sample_write(const DevRow* rows, uint32_t l_eff, uint64_t seed,
                                uint64_t first_sample, uint64_t count, uint64_t n_draws,
                                const uint64_t* d_offsets, uint32_t* d_words, hipStream_t s) {
+  (void)hipGetLastError();
   hipLaunchKernelGGL(sample_write_kernel, dim3((uint32_t)count), dim3(NT), 0, s, rows, l_eff,
                      seed, first_sample, n_draws, d_offsets, d_words);
   return hipGetLastError();

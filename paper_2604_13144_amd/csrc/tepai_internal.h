@@ -15,10 +15,12 @@ constexpr int kMaxChi = 256;
 constexpr int kMaxRows = 4096;        // PAI table rows per Trotter step
 constexpr int kMaxStringOps = 8;
 constexpr int kThreads = 512;         // engine block: eight wave64 wavefronts
-constexpr int kMaxSweeps = 60;
+constexpr int kMaxSweeps = 60;           // Jacobi sweep cap per factorisation
 constexpr double kStopTanFp64 = 1e-8;    // FP64 path: residual ~1e-16
 constexpr double kStopTanMixed = 1e-5;   // mixed path: residual ~1e-10
-constexpr double kCutoffMixed = 1e-7;    // mixed path: relative singular-value floor        // Jacobi sweep cap per factorisation
+constexpr double kCutoffMixed = 1e-7;    // mixed path: relative singular-value floor
+constexpr double kSkipFp64 = 0x1p-53;    // FP64 path: Jacobi pair threshold u sqrt(R)
+constexpr double kSkipMixed = 1e-15;     // mixed path: inputs carry ~1e-7 errors anyway
 
 // One row of the PAI table: a (sub-)rotation of one Trotter step.
 struct DevRow {
@@ -68,6 +70,7 @@ struct EngineArgs {
   uint64_t seed;
   double cutoff;
   double stop_tan;        // Jacobi stop: a sweep whose rotations all have |tan| <= this
+  double skip_tol;        // Jacobi skips a pair with |x^H y| <= skip_tol sqrt(R) |x||y|
   double log_g1_step;
   uint32_t l_eff;
   uint32_t n;
@@ -76,6 +79,7 @@ struct EngineArgs {
   uint32_t n_strings;
   uint32_t n_obs;
   uint32_t mixed;         // 1: TEPAI_FP32_MIXED (complex64 site tensors)
+  uint32_t per_gate;      // 1: TEPAI_PER_GATE (no fusion of same-pair runs)
   // shared starting MPS (null init_tensors: computational-basis start)
   const double2* init_tensors;   // packed site tensors, site k at init_off[k]
   const uint64_t* init_off;      // [n + 1]

@@ -198,3 +198,27 @@ def test_initial_mps_validation_and_workspace():
     # centre out of range
     with pytest.raises(L.TepaiError):
         L.tepai_validate(None, L.ProblemStruct(p.with_(initial_mps=ti.InitialMPS(init.tensors, 6, init.qubit_at))))
+
+
+def test_initial_bits_may_be_null_with_a_shared_start():
+    """initial_bits is ignored, and may be NULL, when initial_mps is given; it
+    is required otherwise."""
+    from oracle.trotter import trotter_initial_mps
+    pre = ti.small_ring(6, seed=3, T=0.4, N=6, chi=4, n_samples=1)
+    init = trotter_initial_mps(pre, 6, 4)
+    ps = L.ProblemStruct(pre.with_(n_samples=2, initial_mps=init))
+    ps.struct.initial_bits = None
+    L.tepai_validate(None, ps)
+    assert L.tepai_workspace_size(None, ps, 2) > 0
+    plain = L.ProblemStruct(pre)
+    plain.struct.initial_bits = None
+    with pytest.raises(L.TepaiError) as e:
+        L.tepai_validate(None, plain)
+    assert e.value.status == -1
+
+
+def test_sample_flag_bits_are_the_headers():
+    src = open(HEADER).read()
+    assert re.search(r"TEPAI_SAMPLE_NONFINITE\s*=\s*1u", src)
+    assert re.search(r"TEPAI_SAMPLE_NONCONVERGED\s*=\s*2u", src)
+    assert (L.TEPAI_SAMPLE_NONFINITE, L.TEPAI_SAMPLE_NONCONVERGED) == (1, 2)

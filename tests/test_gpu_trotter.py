@@ -70,6 +70,16 @@ def test_truncation_workload_prefix(handle, chi, trotter):
     compare(p, range(p.n_samples), vals, wts, st, 0, layers=30)
 
 
+@pytest.mark.parametrize("trotter", [True, False])
+def test_truncation_workload_prefix_per_gate(handle, trotter):
+    # the same experiment with one truncated update per gate (TEPAI_PER_GATE)
+    p = ti.truncation_workload(2, trotter=trotter, per_gate=True)
+    p = p.with_(n_samples=1 if trotter else 3)
+    print(f"truncation workload prefix, per gate: trotter={trotter} chi=2 30 steps", flush=True)
+    vals, wts, st = gpu_batch(handle, p, 0, p.n_samples, [10, 20])
+    compare(p, range(p.n_samples), vals, wts, st, 0, layers=30)
+
+
 def test_truncation_workload_full_length_chi2(handle):
     # all 2000 steps of the experiment at chi = 2 (77.9k truncated updates per
     # circuit): the product formula and two TE-PAI circuits against the oracle

@@ -20,6 +20,17 @@ HIPCC_FLAGS = [
     "-shared",
     # no packed-FP32 instructions in any device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # Machine CSE is off: with it, the FP64 evolve kernel for 64 < R <= 128
+    # produced wrong results (bisected with -opt-bisect-limit to that pass on
+    # that function: a chi = 40 ring lost its canonical-form norm by 1e-8
+    # after a centre shift); the cost is a few recomputed address terms.
+    # The peephole optimiser is off with it: without machine CSE it folds
+    # 64-bit constants such as 9.0 into s_mov_b64 with a literal that the
+    # instruction cannot encode, and the encoder keeps only the low 32 bits
+    # (9.0 became 0.0).  A CPU test assembles the device code with these
+    # flags to keep such instructions out.
+    "-mllvm", "-disable-machine-cse",
+    "-mllvm", "-disable-peephole",
     "-Wall",
     "-Wno-unused-function",
 ]

@@ -9,10 +9,8 @@
   N = 1024, Delta = pi/512 segment, <Z_i> for all i and the half-ring sum of
   Z_i Z_{i+1}.
 
-Both precisions are compared with one oracle pass per sample: circuits,
-signs, weights and update counts exactly; values to 1e-10 (FP64, near-tie
-rule) and 1e-4 (mixed), or, for tie-flagged samples, to the sum of the two
-trajectories' truncation bounds.
+Both precisions are compared with one oracle pass per sample with the bars
+of ``tests/parity.py``; every test checks at least one sample by value.
 """
 import pytest
 
@@ -33,7 +31,7 @@ def handle():
 def test_plain_batched_ring_n32_chi64_prefix(handle):
     p = ti.config(2).with_(n_samples=3)
     print("config shape: heisenberg n=32 chi=64, 24 steps", flush=True)
-    check_both_precisions(handle, p, 24, [10, 14])
+    assert check_both_precisions(handle, p, 24, [10, 14]) >= 1
 
 
 def test_long_time_ring_n100_shared_start_prefix(handle):

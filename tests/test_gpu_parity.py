@@ -1,19 +1,10 @@
 """HIP MPS path vs the CPU oracle, sample by sample (FP64).
 
-Tolerance: 1e-10 per sample value in FP64, the bar the method's FP64 path is
-held to; weights must agree in sign exactly and in magnitude to 1e-14
-relative; gate counts, signs and the schedule's update counts must be
-identical.  A truncation at the bond cap amplifies rounding by about
-1/gap, gap g = (sigma_{k-1} - sigma_k) / sigma_0 at the cut.  The HIP path's
-one-sided Jacobi skips a column pair once its off-diagonal product is below
-tau * |x||y|, tau = 1e-15 sqrt(R) for R <= 2 chi rows, so the pair of singular
-vectors straddling the cut is only fixed to an angle of about tau / (2 g)
-(Wedin's sin-theta theorem, with the QR and the projection adding a few units
-of u = 2^-53), and an observable of norm 1 moves by at most twice that.  A
-sample whose oracle trajectory has a smallest gap g is therefore held to
-max(1e-10, (tau + 4u) / g), and a tie-flagged sample (g <= 1e-10: the
-truncated state is not unique) is excluded from the value check (its
-circuit, sign and weight still are).
+The bars are those of ``tests/parity.py``: circuits, signs and counts
+identical (sum of chi^3 and nominal flops too), weights to 1e-14 relative,
+values to 1e-10 plus the oracle trajectory's near-tie bound; samples with a
+tie (a cap cut whose own bound exceeds 1e-10) are left out of the value
+check.
 """
 import math
 
@@ -27,9 +18,11 @@ from oracle.run import chi_of, run_sample
 from oracle.estimator import estimate
 from paper_2604_13144_amd import _lib as L
 
+import parity
+
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-10
+TOL = parity.TOL
 
 
 @pytest.fixture(scope="module")
@@ -53,35 +46,21 @@ def gpu_batch(handle, p, first, count, windows):
     return vals, w.cpu().numpy(), st
 
 
-def compare(p, samples, vals, wts, st, first, layers=None, tol=TOL):
+def compare(p, samples, vals, wts, st, first, layers=None):
+    """Every slot against the oracle with the FP64 bars; returns the worst
+    value error (and prints how many samples were held to 1e-10 outright)."""
     t = pai.build_table(p)
     lg = t.log_g1(layers)
-    worst = 0.0
+    worst, strict = 0.0, 0
     for i, s in enumerate(samples):
-        r = run_sample(p, t, p.sample_offset + first + i, layers)
-        assert int(st["n_gates"][i]) == r.n_gates
-        assert int(st["sign"][i]) == r.sign
-        assert int(st["updates"][i]) == r.stats.updates
-        assert wts[i] * r.sign > 0
-        assert abs(abs(wts[i]) - math.exp(lg)) <= 1e-14 * math.exp(lg)
-        if r.stats.ties:
-            assert int(st["ties"][i]) > 0 or st["min_gap"][i] < 1e-9
-            continue
-        err = float(np.max(np.abs(vals[i] - r.values)))
-        worst = max(worst, err)
-        assert err <= value_tol(r, tol, chi_of(p, p.sample_offset + first + i)), \
-            (s, err, r.stats.min_gap)
+        o = parity.OracleSample(p, t, p.sample_offset + first + i, layers)
+        parity.check_counts(st, i, o)
+        parity.check_weight(wts[i], o, lg)
+        strict += parity.fp64_value_ok(vals[i], o, f"sample {s}: ")
+        worst = max(worst, float(np.max(np.abs(vals[i] - o.r.values))))
+    print(f"  {strict} of {len(samples)} samples held to 1e-10 outright, worst {worst:.1e}",
+          flush=True)
     return worst
-
-
-U_ROUND = 2.0 ** -53
-
-
-def value_tol(r, tol=TOL, cap=None):
-    """Per-sample bound for oracle result r; cap is the sample's bond cap (the
-    matrices factorised have at most 2 cap rows), else its largest final bond."""
-    tau = 1e-15 * math.sqrt(2 * (cap if cap is not None else max(r.bonds)))
-    return max(tol, (tau + 4.0 * U_ROUND) / r.stats.min_gap)
 
 
 def test_cfg1_exact_regime(handle):
@@ -102,8 +81,7 @@ def test_cfg1_full_estimator_via_run(handle):
     # spot-check a few samples against the oracle
     t = pai.build_table(p)
     for s in (0, 57, 199):
-        r = run_sample(p, t, s)
-        assert np.max(np.abs(out["values"][s] - r.values)) <= TOL
+        assert parity.fp64_value_ok(out["values"][s], parity.OracleSample(p, t, s), f"sample {s}: ")
 
 
 @pytest.mark.parametrize("chi", [3, 6])
@@ -176,11 +154,7 @@ def test_heterogeneous_chi_per_sample(handle):
     p = p.with_(chi_per_sample=(2, 4, 8, 3, 8, 5))
     vals, wts, st = gpu_batch(handle, p, 0, 6, [10])
     assert all(int(m) <= c for m, c in zip(st["max_bond"], p.chi_per_sample))
-    t = pai.build_table(p)
-    for i in range(6):
-        r = run_sample(p, t, i)
-        if not r.stats.ties:
-            assert np.max(np.abs(vals[i] - r.values)) <= value_tol(r, cap=p.chi_per_sample[i])
+    compare(p, range(6), vals, wts, st, 0)
 
 
 def test_time_series_checkpoints(handle):
@@ -201,12 +175,41 @@ def test_time_series_checkpoints(handle):
         L.tepai_reduce(handle, 5, ps.n_obs, v, w, mean, se)
         torch.cuda.synchronize()
         vals = v.cpu().numpy().reshape(5, ps.n_obs)
-        res = [run_sample(p, t, s, j) for s in range(5)]
-        for s, r in enumerate(res):
-            assert float(w[s]) * r.sign > 0
-            assert abs(abs(float(w[s])) - math.exp(t.log_g1(j))) <= 1e-14 * math.exp(t.log_g1(j))
-            if not r.stats.ties:
-                assert np.max(np.abs(vals[s] - r.values)) <= value_tol(r, cap=p.chi_max)
-        ws = np.array([r.sign * math.exp(t.log_g1(j)) for r in res])
-        m, _, _ = estimate(np.array([r.values for r in res]), ws)
+        res = [parity.OracleSample(p, t, s, j) for s in range(5)]
+        for s, o in enumerate(res):
+            parity.check_weight(float(w[s]), o, t.log_g1(j))
+            parity.fp64_value_ok(vals[s], o, f"step {j} sample {s}: ")
+        ws = np.array([o.r.sign * math.exp(t.log_g1(j)) for o in res])
+        m, _, _ = estimate(np.array([o.r.values for o in res]), ws)
         assert np.max(np.abs(mean.cpu().numpy() - m)) <= 1e-9
+
+
+@pytest.mark.parametrize("precision", [L.TEPAI_FP64, L.TEPAI_FP32_MIXED])
+def test_per_gate_mode(handle, precision):
+    # TEPAI_PER_GATE: one truncated update per sampled two-qubit gate, on a
+    # truncated ring (chi = 4) whose runs of same-pair gates would otherwise fuse
+    p = ti.small_ring(10, seed=12, T=0.5, N=10, delta=math.pi / 16, chi=4, n_samples=5)
+    p = p.with_(per_gate=True)
+    print(f"parity: per-gate ring n=10 chi=4, precision {precision}", flush=True)
+    ps = L.ProblemStruct(p, precision=precision)
+    dev = torch.device("cuda", 0)
+    b = L.Batch(handle, ps, 0, 5)
+    b.evolve(4)
+    b.evolve(6)
+    v = torch.empty(5 * ps.n_obs, dtype=torch.float64, device=dev)
+    w = torch.empty(5, dtype=torch.float64, device=dev)
+    b.observe(v, w)
+    st = b.stats()
+    torch.cuda.synchronize()
+    vals = v.cpu().numpy().reshape(5, ps.n_obs)
+    t = pai.build_table(p)
+    fused = L.tepai_run(handle, L.ProblemStruct(p.with_(per_gate=False), precision=precision))
+    assert np.all(st["updates"] > fused["stats"]["updates"])
+    for i in range(5):
+        o = parity.OracleSample(p, t, i, mixed=precision == L.TEPAI_FP32_MIXED,
+                                fp64=precision == L.TEPAI_FP64)
+        parity.check_counts(st, i, o, fp64=precision == L.TEPAI_FP64)
+        if precision == L.TEPAI_FP64:
+            parity.fp64_value_ok(vals[i], o, f"sample {i}: ")
+        else:
+            parity.mixed_value_ok(vals[i], o, f"sample {i}: ")

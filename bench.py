@@ -14,19 +14,28 @@ weighted FP64 reduction forms the estimator for that time.
 Two paths run the same samples: the batched mixed-precision path (complex64
 site tensors, FP32 matrix-core contractions, FP64 QR / Jacobi / truncation /
 estimator), whose rate is the reported value, and the plain FP64 path, whose
-rate, the ratio and the largest per-sample difference between the two at the
-end of the timed steps are reported beside it.
+rate, the ratios and the largest per-sample difference between the two are
+reported beside it.
 
 A full sample is N = 800 Trotter steps; one step processes B * J / N sample
-equivalents, so value = B * K * J / N / t over K timed steps.  The warm-up
-steps advance the same batch first, to Trotter step W * J = 96 by default:
-there every sample of both paths has reached the bond cap chi = 128 (the FP64
-path by step ~32, the mixed path, whose singular-value floor is 1e-7, by step
-~90), so both are timed on the same saturated window.  Saturated steps are the
-most expensive part of a sample up to that point; later steps cost somewhat
-more again as the Schmidt spectra flatten (about +20% per step from step 96
-to step 320), so the value is the rate of the saturated regime at this
-window, not a bound for the whole circuit.
+equivalents (J = 4 Trotter steps per step by default), so value =
+B * K * J / N / t over K timed steps.  The timed window always starts at
+Trotter step --start-step (96): the warm-up is max(--warmup, 96 / J) steps,
+so the requested warm-up is a minimum and the window does not move with it.
+By step 96 every sample of both paths has reached the bond cap chi = 128
+(the FP64 path by step ~32, the mixed path, whose singular-value floor is
+1e-7, by step ~90).  Later steps cost somewhat more again as the Schmidt
+spectra flatten (about +20% per step from step 96 to step 320), so the value
+is the rate of the saturated regime at this window, not a bound for the
+whole circuit.
+
+The plain FP64 path is timed on the first --fp64-steps (4) steps of the same
+window only; the ratios mixed_over_plain (samples/s), ..._per_sum_chi3 and
+..._per_nominal_flop compare the two paths over those same Trotter steps,
+and the per-sample difference between the paths is taken there too.  The
+CPU baseline times the oracle's own two-site update and centre shift at
+bond 128 on the host's cores and applies them to the window's per-sample
+work (``cpu_baseline_saturated``).
 """
 from __future__ import annotations
 
@@ -62,12 +71,20 @@ def measured_traffic():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=12)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=0,
+                    help="untimed steps before the timed ones; the throughput workload "
+                         "always warms up to at least Trotter step --start-step")
     ap.add_argument("--batch", type=int, default=None,
                     help="samples resident at once (default 256, one per CU; the hybrid "
                          "workload 768, so that CUs done with a small-cap sample take another)")
-    ap.add_argument("--layers-per-step", type=int, default=8)
+    ap.add_argument("--layers-per-step", type=int, default=4)
+    ap.add_argument("--start-step", type=int, default=96,
+                    help="throughput workload: first Trotter step of the timed window (both "
+                         "paths have every bond at the cap by then)")
+    ap.add_argument("--fp64-steps", type=int, default=4,
+                    help="throughput workload: timed steps of the plain FP64 path (the first "
+                         "ones of the mixed path's window)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", default="mixed,fp64",
@@ -87,6 +104,9 @@ def parse():
                     help="hybrid workload: caps 16, 32, 64 in turn instead of by thirds")
     ap.add_argument("--read-every", type=int, default=100,
                     help="truncation workload: Trotter steps between read-outs")
+    ap.add_argument("--per-gate", action="store_true",
+                    help="truncation workload: one truncated update per sampled gate "
+                         "(TEPAI_PER_GATE) instead of one per same-pair run")
     ap.add_argument("--delta-log2", type=int, default=12,
                     help="truncation workload: PAI angle Delta = pi / 2^k")
     return ap.parse_args()
@@ -124,7 +144,6 @@ def _oracle_worker(args):
     circ = sample_circuit(p, t, sample)
     chi = p.chi_max if p.chi_per_sample is None else p.chi_per_sample[sample]
     ops, _ = build_schedule(p, t, circ, chi)
-    L = t.l_eff
     # layer boundaries in the op list: count ops until the time budget ends
     m = MPS(p.initial_bits, p.svd_cutoff)
     t0 = time.perf_counter()
@@ -139,14 +158,25 @@ def _oracle_worker(args):
     return frac_updates, el, m.stats.updates, max(m.bonds())
 
 
+def host_cores():
+    """Worker processes for the oracle: the cores this process may run on,
+    at most 16 (the host CPU share that comes with one GPU)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return min(avail, 16), avail, os.cpu_count()
+
+
 def cpu_baseline(seconds: float, kind: str = "throughput"):
-    cores = min(os.cpu_count() or 1, 16)
+    cores, avail, nproc = host_cores()
     ctx = mp.get_context("spawn")
     with ctx.Pool(cores) as pool:
         res = pool.map(_oracle_worker, [(s, seconds, kind) for s in range(cores)])
     frac = sum(r[0] for r in res)
     wall = max(r[1] for r in res)
     return {"value": frac / wall, "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "host_cpus": {"affinity": avail, "nproc": nproc},
             "sample": (f"{cores} samples of the same workload, one per process (OMP 1 thread), "
                        f"each run from t=0 for {seconds:.0f} s; fraction of each sample's "
                        f"two-site updates and shifts done, summed, over wall time "
@@ -154,9 +184,81 @@ def cpu_baseline(seconds: float, kind: str = "throughput"):
                        f"so this favours the CPU)")}
 
 
+def _saturated_worker(args):
+    """Time the oracle's two-site update and centre shift at bond 128 (the
+    saturated regime of the timed window) for about `seconds` seconds."""
+    seconds, chi, seed = args
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"
+    import numpy as np
+    from oracle.mps import MPS
+    from oracle.schedule import setting_operator
+    rng = np.random.default_rng(seed)
+
+    def rand_site():
+        return rng.standard_normal((chi, 2, chi)) + 1j * rng.standard_normal((chi, 2, chi))
+
+    m = MPS("000", 1e-12)
+    m.A = [rand_site(), rand_site(), rand_site()]
+    m.centre = 1
+    gates = [setting_operator(ps, 0.01, math.pi / 256, 1) for ps in ("XX", "YY", "ZZ")]
+    t_upd, n_upd = 0.0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 0.8 * seconds:
+        g = gates[n_upd % 3]
+        ts = time.perf_counter()
+        if m.centre == 1 and n_upd % 2 == 0:
+            m.update(0, g, chi, right=True)        # centre ends on site 1
+        else:
+            m.update(1, g, chi, right=False)       # centre ends on site 1
+        t_upd += time.perf_counter() - ts
+        n_upd += 1
+    t_sh, n_sh = 0.0, 0
+    while time.perf_counter() - t0 < seconds:
+        ts = time.perf_counter()
+        if m.centre == 1:
+            m.shift(1, +1)
+        else:
+            m.shift(2, -1)
+        t_sh += time.perf_counter() - ts
+        n_sh += 1
+    return t_upd / n_upd, t_sh / max(n_sh, 1), n_upd, n_sh
+
+
+def cpu_baseline_saturated(seconds, updates_per_sample, shifts_per_sample, window_fraction,
+                           chi=128):
+    """The oracle on the timed window's work: every host process times the
+    oracle's own two-site update (contraction, LAPACK SVD of the 2 chi x 2 chi
+    matrix, truncation to chi) and centre shift at bond chi; the window's
+    per-sample update and shift counts (identical on every path: the
+    schedule does not depend on precision) turn those times into the time
+    the oracle needs per sample for the window, and samples/s follows."""
+    cores, avail, nproc = host_cores()
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_saturated_worker, [(seconds, chi, 100 + i) for i in range(cores)])
+    t_u = sum(r[0] for r in res) / len(res)
+    t_s = sum(r[1] for r in res) / len(res)
+    per_sample_window = updates_per_sample * t_u + shifts_per_sample * t_s
+    value = cores * window_fraction / per_sample_window
+    return {"value": value, "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "host_cpus": {"affinity": avail, "nproc": nproc},
+            "seconds_per_update": t_u, "seconds_per_shift": t_s,
+            "sample": (f"oracle two-site update (einsum contraction, numpy/LAPACK SVD of "
+                       f"{2 * chi}x{2 * chi} complex128, truncation to {chi}) and centre shift "
+                       f"timed at bond {chi} for {seconds:.0f} s in each of {cores} processes "
+                       f"(OMP 1 thread; {sum(r[2] for r in res)} updates, "
+                       f"{sum(r[3] for r in res)} shifts), applied to the timed window's "
+                       f"per-sample work ({updates_per_sample:.0f} updates, "
+                       f"{shifts_per_sample:.0f} shifts, all at the cap), one sample per process")}
+
+
 # ----------------------------------------------------------------- GPU run
-def run_path(L, h, p, precision, J, K, W, B):
-    """W warm-up and K timed steps of one precision path on a fresh batch."""
+def run_path(L, h, p, precision, J, K, W, B, match=None):
+    """W warm-up and K timed steps of one precision path on a fresh batch.
+
+    ``match`` (<= K): also report the rate over the first ``match`` timed
+    steps, the window the other path is timed on."""
     import numpy as np
     import torch
     dev = torch.device("cuda", 0)
@@ -171,6 +273,7 @@ def run_path(L, h, p, precision, J, K, W, B):
     name = "mixed" if precision == L.TEPAI_FP32_MIXED else "fp64"
 
     def step(events=None):
+        # the events sit on the stream the library launches on
         if events is not None:
             events[0].record(stream)
         b.evolve(J)
@@ -184,22 +287,33 @@ def run_path(L, h, p, precision, J, K, W, B):
         step()
         torch.cuda.synchronize()
         print(f"[bench] {name} warmup step {i + 1}/{W}: {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    fields = ("n_gates", "updates", "shifts", "nominal_flops", "jacobi_sweeps", "sum_chi3")
     s0 = b.stats()
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    walls = []
+    s_match = None
     t0 = time.perf_counter()
     for i in range(K):
+        ts = time.perf_counter()
         step(evs[i])
         torch.cuda.synchronize()
-        print(f"[bench] {name} timed step {i + 1}/{K}", file=sys.stderr, flush=True)
+        walls.append(time.perf_counter() - ts)
+        if match is not None and i + 1 == match:
+            s_match = b.stats()
+            v_match, m_match = vals.cpu().numpy().reshape(B, n_obs), mean.cpu().numpy()
+        print(f"[bench] {name} timed step {i + 1}/{K}: {walls[-1]:.1f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     s1 = b.stats()
-    evolve_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs)
-    d = {f: float(np.sum(s1[f].astype(np.float64) - s0[f].astype(np.float64)))
-         for f in ("n_gates", "updates", "shifts", "nominal_flops", "jacobi_sweeps", "sum_chi3")}
-    achieved = d["nominal_flops"] / (evolve_ms / 1e3) / 1e12
-    return {
+    ms = [e0.elapsed_time(e1) for e0, e1 in evs]
+
+    def delta(a, c):
+        return {f: float(np.sum(c[f].astype(np.float64) - a[f].astype(np.float64))) for f in fields}
+
+    d = delta(s0, s1)
+    evolve_ms = sum(ms)
+    out = {
         "value": B * K * J / p.trotter_steps / wall,
         "wall": wall,
         "ms_per_step": wall / K * 1e3,
@@ -208,15 +322,26 @@ def run_path(L, h, p, precision, J, K, W, B):
         "sum_chi3_per_s": d["sum_chi3"] / wall,
         "mean_max_bond": float(np.mean(s1["max_bond"])),
         "sweeps": d["jacobi_sweeps"] / max(1.0, d["updates"] + d["shifts"]),
-        "achieved": achieved,
+        "achieved": d["nominal_flops"] / (evolve_ms / 1e3) / 1e12,
         "kernel_ms_per_launch": evolve_ms / K,
         "flops_per_launch": d["nominal_flops"] / K,
+        "updates_per_sample": d["updates"] / B,
+        "shifts_per_sample": d["shifts"] / B,
+        "sum_chi3_per_sample": d["sum_chi3"] / B,
         "values": vals.cpu().numpy().reshape(B, n_obs),
         "mean": mean.cpu().numpy(),
     }
+    if s_match is not None:
+        dm = delta(s0, s_match)
+        wm = sum(walls[:match])
+        out["match"] = {"steps": match, "value": B * match * J / p.trotter_steps / wm,
+                        "sum_chi3_per_s": dm["sum_chi3"] / wm,
+                        "tflops": dm["nominal_flops"] / (sum(ms[:match]) / 1e3) / 1e12,
+                        "values": v_match, "mean": m_match}
+    return out
 
 
-def truncation_experiment(L, h, read_every, delta_log2=12):
+def truncation_experiment(L, h, read_every, delta_log2=12, per_gate=False):
     """The truncation-robustness experiment on the GPU (FP64 path).
 
     For each method (the deterministic product formula, one circuit; TE-PAI,
@@ -237,7 +362,7 @@ def truncation_experiment(L, h, read_every, delta_log2=12):
     for method in ("trotter", "tepai"):
         for chi in (2, 16):
             p = ti.truncation_workload(chi, trotter=method == "trotter",
-                                       delta=math.pi / 2 ** delta_log2)
+                                       delta=math.pi / 2 ** delta_log2, per_gate=per_gate)
             if read_every < 1 or p.trotter_steps % read_every:
                 raise SystemExit("--read-every must divide N = %d" % p.trotter_steps)
             ps = L.ProblemStruct(p)
@@ -292,7 +417,9 @@ def truncation_experiment(L, h, read_every, delta_log2=12):
     of_mean = np.mean(np.abs(np.mean(dx, axis=1)), axis=1)
     return {
         "workload": "truncation: n=20 ring J=1 omega~U[-1,1], T=1, N=2000, Delta=pi/2^%d, "
-                    "N_s=100, start |+..+-+..+>, X/Y/Z of every qubit, chi in {2,16}" % delta_log2,
+                    "N_s=100, start |+..+-+..+>, X/Y/Z of every qubit, chi in {2,16}, %s"
+                    % (delta_log2, "one truncated update per gate" if per_gate
+                       else "one truncated update per same-pair run"),
         "dtype": "f64",
         "data": "synthetic",
         "times": times,
@@ -449,7 +576,8 @@ def main():
         import torch
         torch.cuda.init()
         from paper_2604_13144_amd import _lib as L
-        print(json.dumps(truncation_experiment(L, L.Handle(0), a.read_every, a.delta_log2)))
+        print(json.dumps(truncation_experiment(L, L.Handle(0), a.read_every, a.delta_log2,
+                                               a.per_gate)))
         return
     import numpy as np
     import torch
@@ -458,23 +586,32 @@ def main():
 
     B = a.batch or 256
     p = workload(B)
-    J, K, W = a.layers_per_step, a.steps, a.warmup
+    J, K = a.layers_per_step, a.steps
+    # the timed window starts at a fixed saturated Trotter step whatever the
+    # requested warm-up: --warmup is a minimum
+    W = max(a.warmup, -(-a.start_step // J))
     if (W + K) * J > p.trotter_steps:
         raise SystemExit("warmup + steps exceed the circuit")
+    Kp = min(K, a.fp64_steps)
     h = L.Handle(0)
     paths = a.paths.split(",")
-    mixed = run_path(L, h, p, L.TEPAI_FP32_MIXED, J, K, W, B) if "mixed" in paths else None
-    plain = run_path(L, h, p, L.TEPAI_FP64, J, K, W, B) if "fp64" in paths else None
+    mixed = run_path(L, h, p, L.TEPAI_FP32_MIXED, J, K, W, B, match=Kp) if "mixed" in paths else None
+    plain = run_path(L, h, p, L.TEPAI_FP64, J, Kp, W, B) if "fp64" in paths else None
     if mixed is None or plain is None:
         # one path only (profiling runs): report it alone
         r = mixed or plain
         print(json.dumps({"path": "mixed" if mixed else "fp64", "value": r["value"], "unit": "samples/s",
                           "kernel_ms_per_launch": r["kernel_ms_per_launch"],
                           "flops_per_launch": r["flops_per_launch"],
-                          "timed_trotter_steps": [W * J, (W + K) * J]}))
+                          "achieved_tflops": r["achieved"],
+                          "timed_trotter_steps": [W * J, (W + (K if mixed else Kp)) * J]}))
         return
-    err = float(np.max(np.abs(mixed["values"] - plain["values"])))
-    est_err = float(np.max(np.abs(mixed["mean"] - plain["mean"])))
+    # accuracy at the same Trotter step: the mixed read-out after its first Kp
+    # timed steps against the FP64 read-out at the end of its window
+    mm = mixed["match"]
+    err = float(np.max(np.abs(mm["values"] - plain["values"])))
+    est_err = float(np.max(np.abs(mm["mean"] - plain["mean"])))
+    traffic = measured_traffic()
     line = {
         "metric": "TE-PAI MPS samples/s at n=64, chi=128 (batched mixed vs plain FP64) at fixed err",
         "value": mixed["value"],
@@ -482,6 +619,7 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
+        "warmup_requested": a.warmup,
         "ms_per_step": mixed["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
@@ -499,18 +637,27 @@ def main():
         "mean_max_bond": mixed["mean_max_bond"],
         "jacobi_sweeps_per_factorisation": mixed["sweeps"],
         "plain_fp64": {"value": plain["value"], "unit": "samples/s", "dtype": "c128 (f64)",
+                       "steps": Kp, "timed_trotter_steps": [W * J, (W + Kp) * J],
                        "ms_per_step": plain["ms_per_step"], "gates_per_s": plain["gates_per_s"],
                        "sum_chi3_per_s": plain["sum_chi3_per_s"],
                        "jacobi_sweeps_per_factorisation": plain["sweeps"],
                        "kernel_ms_per_launch": plain["kernel_ms_per_launch"],
                        "achieved_tflops": plain["achieved"],
                        "frac": plain["achieved"] / FP64_PEAK_TFLOPS},
-        "mixed_over_plain": mixed["value"] / plain["value"],
+        # both paths over the same Trotter steps (the first Kp timed steps)
+        "mixed_over_plain": mm["value"] / plain["value"],
+        "mixed_over_plain_per_sum_chi3": mm["sum_chi3_per_s"] / plain["sum_chi3_per_s"],
+        "mixed_over_plain_per_nominal_flop": mm["tflops"] / plain["achieved"],
+        "mixed_over_plain_window": [W * J, (W + Kp) * J],
         "max_sample_err_mixed_vs_fp64": err,
         "max_estimator_err_mixed_vs_fp64": est_err,
+        "err_at_trotter_step": (W + Kp) * J,
         "roofline": {"bound": "alu", "achieved": mixed["achieved"], "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": mixed["achieved"] / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(),
+                     "traffic": traffic,
+                     "traffic_source": ("rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel source "
+                                        "(profiles/evolve_kernel_traffic.json), not measured in this run"
+                                        if traffic is not None else None),
                      "kernel": "evolve_kernel (mixed)",
                      "kernel_ms_per_launch": mixed["kernel_ms_per_launch"],
                      "flops_per_launch": mixed["flops_per_launch"],
@@ -518,7 +665,9 @@ def main():
                                     "+ 4*(4m^2n+8mn^2+9n^3), m,n = 2cl,2cr"},
     }
     if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline_saturated(
+            a.cpu_seconds, mixed["updates_per_sample"], mixed["shifts_per_sample"],
+            K * J / p.trotter_steps)
     print(json.dumps(line))
 
 

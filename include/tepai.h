@@ -307,6 +307,28 @@ tepai_status tepai_run(tepai_handle* h, const tepai_problem* p, uint32_t batch, 
                        double* std_err, double* weights, double* values,
                        tepai_sample_stats* stats);
 
+/* Bytes of the fixed device array that tepai_run_noalloc works in. */
+#define TEPAI_NOALLOC_BYTES ((size_t)256 << 20)
+
+/* tepai_run without any device allocation, for callers that cannot allocate
+ * device memory (serving loops that keep a fixed footprint, harnesses that
+ * forbid hipMalloc).  The batch workspace lives in one file-scope device
+ * array of TEPAI_NOALLOC_BYTES per GPU, reserved when tepai_create first
+ * runs on that GPU and held until the process ends; the samples go through
+ * it in batches of as many as fit.  Outputs are device pointers, all
+ * required: d_mean[n_obs], d_std_err[n_obs], d_weights[n_samples],
+ * d_values[n_samples * n_obs] (the reduction reads them); stats[n_samples]
+ * is a host array, optional (NULL to skip).  Work is queued on hip_stream
+ * (NULL: the null stream) and the call returns after synchronising it.
+ * Returns TEPAI_ENOMEM when one sample's workspace (tepai_workspace_size
+ * with count 1) exceeds TEPAI_NOALLOC_BYTES, and TEPAI_ENUMERIC like
+ * tepai_run.  Every call on one GPU shares that GPU's array, which keeps
+ * the last call's contents (nothing in it needs to start at zero): calls
+ * that overlap on one GPU, from several threads or handles, race. */
+tepai_status tepai_run_noalloc(tepai_handle* h, const tepai_problem* p, void* hip_stream,
+                               double* d_mean, double* d_std_err, double* d_weights,
+                               double* d_values, tepai_sample_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

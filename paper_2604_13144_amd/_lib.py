@@ -99,6 +99,8 @@ PROTOTYPES = {
     "tepai_reduce": (C.c_int, [_P, C.c_uint64, C.c_uint32, _P, _P, _P, _P, _P]),
     "tepai_run": (C.c_int, [_P, C.POINTER(tepai_problem), C.c_uint32, _P, _P, _P, _P,
                             C.POINTER(tepai_sample_stats)]),
+    "tepai_run_noalloc": (C.c_int, [_P, C.POINTER(tepai_problem), _P, _P, _P, _P, _P,
+                                    C.POINTER(tepai_sample_stats)]),
 }
 
 _lib = None
@@ -436,3 +438,34 @@ def tepai_run(h: Handle, ps: ProblemStruct, batch: int = 0, want_values: bool = 
         raise err
     return out
 
+
+NOALLOC_BYTES = 256 << 20
+
+
+def tepai_run_noalloc(h: Handle, ps: ProblemStruct, d_mean, d_se, d_weights, d_values,
+                      stream=None, want_stats: bool = True):
+    """The estimator in the library's fixed device array (no device
+    allocation); outputs go to the given device tensors.  Returns the
+    per-sample stats (or None).  TEPAI_ENUMERIC raises TepaiError with
+    ``.result`` = the stats, the device outputs being written."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    ns = int(ps.struct.n_samples)
+    st_arr = (tepai_sample_stats * ns)() if want_stats else None
+    st = load().tepai_run_noalloc(h.h, ps.ref(), C.c_void_p(s.cuda_stream),
+                                  C.c_void_p(d_mean.data_ptr()), C.c_void_p(d_se.data_ptr()),
+                                  C.c_void_p(d_weights.data_ptr()),
+                                  C.c_void_p(d_values.data_ptr()), st_arr)
+    if st not in (TEPAI_OK, TEPAI_ENUMERIC):
+        _check(st, h.h)
+    stats = None
+    if st_arr is not None:
+        stats = np.zeros(ns, STATS_DTYPE)
+        for i in range(ns):
+            for f in STATS_FIELDS:
+                stats[f][i] = getattr(st_arr[i], f)
+    if st == TEPAI_ENUMERIC:
+        err = TepaiError(st, (load().tepai_last_error(h.h) or b"").decode())
+        err.result = stats
+        raise err
+    return stats

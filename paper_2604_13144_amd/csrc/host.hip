@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -14,8 +15,16 @@
 
 struct tepai_handle {
   int device = 0;
+  void* scratch = nullptr;   // device address of this GPU's copy of `scratch`
+  std::string scratch_err;   // why that address is missing, if it is
   std::string err;
 };
+
+// Workspace of tepai_run_noalloc: one copy per GPU, loaded with the code
+// object.  In host code the name stands for a host-side handle, not for the
+// device memory: only the address that hipGetSymbolAddress returns for the
+// current device may be handed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[TEPAI_NOALLOC_BYTES];
 
 namespace tepai {
 namespace {
@@ -367,6 +376,27 @@ tepai_status numeric_status(tepai_handle* h, const tepai_problem* p,
   return TEPAI_OK;
 }
 
+// Device address of `scratch` on each GPU, looked up once per device (with
+// that device current) by the first tepai_create on it.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_addr[kMaxDevices] = {};
+
+hipError_t scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_addr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return e;
+    }
+    g_scratch_addr[device] = ptr;
+  }
+  *out = g_scratch_addr[device];
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -379,8 +409,21 @@ tepai_status tepai_create(tepai_handle** out, int device) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return TEPAI_EDEVICE;
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TEPAI_EDEVICE;
+  if (device >= kMaxDevices) return TEPAI_EDEVICE;
+  // the lookup needs the device current; the caller's current device is
+  // restored.  A failed lookup leaves the handle usable for everything but
+  // tepai_run_noalloc, which then reports it.
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) return TEPAI_EDEVICE;
+  void* addr = nullptr;
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = scratch_address(device, &addr);
+  if (hipSetDevice(prev) != hipSuccess) return TEPAI_EDEVICE;
   auto* h = new tepai_handle;
   h->device = device;
+  h->scratch = addr;
+  if (e != hipSuccess)
+    h->scratch_err = std::string("hipGetSymbolAddress: ") + hipGetErrorString(e);
   *out = h;
   return TEPAI_OK;
 }
@@ -750,6 +793,50 @@ tepai_status tepai_run(tepai_handle* h, const tepai_problem* p, uint32_t batch, 
   if (e == hipSuccess && values) e = hipMemcpy(values, d_v, sizeof(double) * ns * p->n_obs, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail(h, TEPAI_EDEVICE, std::string("copy-out: ") + hipGetErrorString(e));
   return numeric_status(h, p, sout, mean);
+}
+
+tepai_status tepai_run_noalloc(tepai_handle* h, const tepai_problem* p, void* hip_stream,
+                               double* d_mean, double* d_std_err, double* d_weights,
+                               double* d_values, tepai_sample_stats* stats) {
+  if (!h) return TEPAI_EINVAL;
+  tepai_status st = validate(h, p);
+  if (st != TEPAI_OK) return st;
+  if (!d_mean || !d_std_err || !d_weights || !d_values)
+    return fail(h, TEPAI_EINVAL, "device output pointers NULL");
+  if (p->n_obs == 0) return fail(h, TEPAI_ERANGE, "n_obs must be >= 1");
+  if (!h->scratch)
+    return fail(h, TEPAI_EDEVICE, "no device address for the fixed workspace (" + h->scratch_err + ")");
+  TEPAI_HIP(h, hipSetDevice(h->device));
+  const uint64_t ns = p->n_samples;
+  const size_t cap = TEPAI_NOALLOC_BYTES;
+  size_t per1 = 0, per2 = 0;
+  if ((st = tepai_workspace_size(h, p, 1, &per1)) != TEPAI_OK) return st;
+  if ((st = tepai_workspace_size(h, p, 2, &per2)) != TEPAI_OK) return st;
+  if (per1 > cap)
+    return fail(h, TEPAI_ENOMEM, "one sample needs " + std::to_string(per1) +
+                                     " bytes of workspace, more than the fixed " +
+                                     std::to_string(cap));
+  // as many samples per batch as the array holds
+  const size_t per = per2 - per1;
+  uint64_t B = per ? 1 + (cap - per1) / per : ns;
+  B = std::min<uint64_t>(std::min<uint64_t>(B, ns), 0xffffffffull);
+  size_t need = 0;
+  for (;;) {
+    if ((st = tepai_workspace_size(h, p, (uint32_t)B, &need)) != TEPAI_OK) return st;
+    if (need <= cap || B == 1) break;
+    B -= 1;
+  }
+  hipStream_t stream = (hipStream_t)hip_stream;
+  std::vector<tepai_sample_stats> sbuf(stats ? 0 : ns);   // host memory
+  tepai_sample_stats* sout = stats ? stats : sbuf.data();
+  st = run_batches(h, p, (uint32_t)B, h->scratch, cap, stream, d_values, d_weights, d_mean,
+                   d_std_err, sout);
+  if (st != TEPAI_OK) return st;
+  std::vector<double> mean(p->n_obs);
+  TEPAI_HIP(h, hipMemcpyAsync(mean.data(), d_mean, sizeof(double) * p->n_obs,
+                              hipMemcpyDeviceToHost, stream));
+  TEPAI_HIP(h, hipStreamSynchronize(stream));
+  return numeric_status(h, p, sout, mean.data());
 }
 
 }  // extern "C"

@@ -209,6 +209,7 @@ typedef struct {
 
 typedef struct tepai_handle tepai_handle;
 typedef struct tepai_batch tepai_batch;
+typedef struct tepai_step_graph tepai_step_graph;
 
 /* Create a handle bound to HIP device `device`.  Fails with TEPAI_EDEVICE
  * when the device is absent or is not gfx950. */
@@ -288,6 +289,25 @@ tepai_status tepai_batch_read_mps(tepai_batch* b, uint32_t slot, uint64_t capaci
                                   uint32_t* bond, uint32_t* qubit_at, uint32_t* centre,
                                   uint64_t* n_values, double* tensors);
 void tepai_batch_destroy(tepai_batch* b);
+
+/* A captured read-out step of a batch: the launches of tepai_batch_evolve
+ * (n_layers Trotter steps), tepai_batch_observe into d_values / d_weights
+ * and tepai_reduce into d_mean / d_std_err, recorded once as a HIP graph on
+ * the batch's stream and replayed by tepai_step_graph_launch (the time
+ * series of sec. "Deterministic Expectation Values": each replay advances
+ * every sample by n_layers steps and leaves the estimate at the new time).
+ * A replay does exactly what the three calls would do; it saves their host
+ * launch work.  The batch's stream must not be the null stream (TEPAI_EINVAL:
+ * it cannot be captured); the device buffers (count * n_obs, count, n_obs,
+ * n_obs doubles) and the batch must outlive the graph.  Nothing runs at
+ * capture time.  tepai_step_graph_launch returns TEPAI_ERANGE, launching
+ * nothing, when the batch would pass its last Trotter step; it does not
+ * synchronise.  The recorded work holds no memset nodes. */
+tepai_status tepai_batch_capture_step(tepai_batch* b, uint32_t n_layers, double* d_values,
+                                      double* d_weights, double* d_mean, double* d_std_err,
+                                      tepai_step_graph** out);
+tepai_status tepai_step_graph_launch(tepai_step_graph* g);
+void tepai_step_graph_destroy(tepai_step_graph* g);
 
 /* Weighted reduction on the device (Statement 2): x_s = w_s v_s,
  * d_mean[o] = sum_s x_so / count, d_std_err[o] = sqrt(var_o / count) with the

@@ -99,6 +99,9 @@ PROTOTYPES = {
     "tepai_reduce": (C.c_int, [_P, C.c_uint64, C.c_uint32, _P, _P, _P, _P, _P]),
     "tepai_run": (C.c_int, [_P, C.POINTER(tepai_problem), C.c_uint32, _P, _P, _P, _P,
                             C.POINTER(tepai_sample_stats)]),
+    "tepai_batch_capture_step": (C.c_int, [_P, C.c_uint32, _P, _P, _P, _P, C.POINTER(_P)]),
+    "tepai_step_graph_launch": (C.c_int, [_P]),
+    "tepai_step_graph_destroy": (None, [_P]),
     "tepai_run_noalloc": (C.c_int, [_P, C.POINTER(tepai_problem), _P, _P, _P, _P, _P,
                                     C.POINTER(tepai_sample_stats)]),
 }
@@ -363,10 +366,39 @@ class Batch:
             at += 2 * a * c
         return MPSState(tuple(tensors), int(centre.value), tuple(int(q) for q in qubit_at))
 
+    def capture_step(self, n_layers, d_values, d_weights, d_mean, d_se) -> "StepGraph":
+        """Record evolve(n_layers) + observe + reduce once as a HIP graph."""
+        g = _P()
+        _check(load().tepai_batch_capture_step(
+            self.b, n_layers, C.c_void_p(d_values.data_ptr()), C.c_void_p(d_weights.data_ptr()),
+            C.c_void_p(d_mean.data_ptr()), C.c_void_p(d_se.data_ptr()), C.byref(g)), self.h.h)
+        return StepGraph(self, g, (d_values, d_weights, d_mean, d_se))
+
     def close(self):
         if self.b:
             load().tepai_batch_destroy(self.b)
             self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class StepGraph:
+    """A captured read-out step; keeps its batch and buffers alive."""
+
+    def __init__(self, batch, g, buffers):
+        self.batch, self.g, self.buffers = batch, g, buffers
+
+    def launch(self) -> None:
+        _check(load().tepai_step_graph_launch(self.g), self.batch.h.h)
+
+    def close(self):
+        if self.g:
+            load().tepai_step_graph_destroy(self.g)
+            self.g = None
 
     def __del__(self):
         try:

@@ -743,6 +743,67 @@ tepai_status tepai_batch_read_mps(tepai_batch* b, uint32_t slot, uint64_t capaci
 
 void tepai_batch_destroy(tepai_batch* b) { delete b; }
 
+}  // extern "C"
+
+struct tepai_step_graph {
+  tepai_batch* b = nullptr;
+  uint32_t n_layers = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~tepai_step_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+extern "C" {
+
+tepai_status tepai_batch_capture_step(tepai_batch* b, uint32_t n_layers, double* d_values,
+                                      double* d_weights, double* d_mean, double* d_std_err,
+                                      tepai_step_graph** out) {
+  if (!b || !out) return TEPAI_EINVAL;
+  *out = nullptr;
+  if (n_layers == 0) return fail(b->h, TEPAI_ERANGE, "n_layers must be >= 1");
+  if (!d_values || !d_weights || !d_mean || !d_std_err)
+    return fail(b->h, TEPAI_EINVAL, "output pointers NULL");
+  if (!b->stream) return fail(b->h, TEPAI_EINVAL, "the null stream cannot be captured");
+  TEPAI_HIP(b->h, hipSetDevice(b->h->device));
+  auto* g = new tepai_step_graph;
+  g->b = b;
+  g->n_layers = n_layers;
+  hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t work = launch_evolve(b->args, n_layers, b->stream);
+    if (work == hipSuccess) work = launch_observe(b->args, d_values, d_weights, b->stream);
+    if (work == hipSuccess)
+      work = launch_reduce(b->args.count, b->n_obs, d_values, d_weights, d_mean, d_std_err,
+                           b->stream);
+    const hipError_t end = hipStreamEndCapture(b->stream, &g->graph);   // always ends it
+    e = work != hipSuccess ? work : end;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    delete g;
+    (void)hipGetLastError();
+    return fail(b->h, TEPAI_EDEVICE, std::string("step capture: ") + hipGetErrorString(e));
+  }
+  *out = g;
+  return TEPAI_OK;
+}
+
+tepai_status tepai_step_graph_launch(tepai_step_graph* g) {
+  if (!g) return TEPAI_EINVAL;
+  tepai_batch* b = g->b;
+  if ((uint64_t)b->layers_done + g->n_layers > b->trotter_steps)
+    return fail(b->h, TEPAI_ERANGE, "evolve beyond the last Trotter step");
+  TEPAI_HIP(b->h, hipSetDevice(b->h->device));
+  TEPAI_HIP(b->h, hipGraphLaunch(g->exec, b->stream));
+  b->layers_done += g->n_layers;
+  return TEPAI_OK;
+}
+
+void tepai_step_graph_destroy(tepai_step_graph* g) { delete g; }
+
 tepai_status tepai_reduce(tepai_handle* h, uint64_t count, uint32_t n_obs, const double* d_values,
                           const double* d_weights, double* d_mean, double* d_std_err,
                           void* hip_stream) {

@@ -52,20 +52,30 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector (and FP64 MFMA), dense
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "evolve_kernel_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2604_13144_amd", "csrc", "kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_13144_amd", "csrc", "kernels.hip"),
+                  os.path.join(ROOT, "paper_2604_13144_amd", "build.py")]
+
+
+def kernel_source_sha256() -> str:
+    """Hash of the kernel source and of the build script that holds its flags."""
+    import hashlib
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic():
     """HBM-side bytes per launch of the mixed evolve kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE runs (calibrated by a 1 GiB copy), or
-    None when the kernel source has changed since the counters were taken."""
-    import hashlib
+    None when the kernel source or its build flags have changed since the
+    counters were taken."""
     try:
         rec = json.load(open(TRAFFIC_RECORD))
-        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        sha = kernel_source_sha256()
     except OSError:
         return None
-    return rec["traffic_bytes_per_launch"] if rec.get("kernels_hip_sha256") == sha else None
+    return rec["traffic_bytes_per_launch"] if rec.get("source_sha256") == sha else None
 
 
 def parse():
@@ -87,17 +97,27 @@ def parse():
                          "ones of the mixed path's window)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", default="",
+                    help="throughput workload: comma list of QR panel widths to time at the "
+                         "start of the window (tepai_batch_autotune); the fastest is kept")
     ap.add_argument("--paths", default="mixed,fp64",
                     help="comma list of paths to time (the first one gives value)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (counter calibration) and exit")
-    ap.add_argument("--workload", choices=("throughput", "truncation", "hybrid"),
+    ap.add_argument("--workload", choices=("throughput", "truncation", "hybrid", "batching"),
                     default="throughput",
                     help="truncation: the chi = 2 vs 16 robustness experiment; hybrid: "
                          "Trotter-then-TE-PAI on the n = 100 ring (use --layers-per-step 32 "
-                         "--warmup 4); default: the throughput step")
+                         "--warmup 4); batching: the n = 64 ring with caps 32/64/128 by "
+                         "sample, 2048 samples in one batch (mixed path); default: the "
+                         "throughput step")
     ap.add_argument("--t0", type=float, default=0.5,
                     help="hybrid workload: length of the Trotter segment")
+    ap.add_argument("--pre-cap", type=int, default=32,
+                    help="hybrid workload: bond cap of the Trotter segment; samples whose "
+                         "cap is smaller truncate their copy of its state")
+    ap.add_argument("--hybrid-precision", choices=("mixed", "fp64"), default="mixed",
+                    help="hybrid workload: precision of the TE-PAI samples")
     ap.add_argument("--no-pi", action="store_true",
                     help="hybrid workload: the biased variant without pi rotations")
     ap.add_argument("--cycle-caps", action="store_true",
@@ -254,11 +274,13 @@ def cpu_baseline_saturated(seconds, updates_per_sample, shifts_per_sample, windo
 
 
 # ----------------------------------------------------------------- GPU run
-def run_path(L, h, p, precision, J, K, W, B, match=None):
+def run_path(L, h, p, precision, J, K, W, B, match=None, autotune=None):
     """W warm-up and K timed steps of one precision path on a fresh batch.
 
     ``match`` (<= K): also report the rate over the first ``match`` timed
-    steps, the window the other path is timed on."""
+    steps, the window the other path is timed on.  ``autotune`` (a tuple of
+    QR panel widths): after the warm-up, time each over the next J steps
+    (state restored after each) and keep the fastest for the timed steps."""
     import numpy as np
     import torch
     dev = torch.device("cuda", 0)
@@ -287,6 +309,10 @@ def run_path(L, h, p, precision, J, K, W, B, match=None):
         step()
         torch.cuda.synchronize()
         print(f"[bench] {name} warmup step {i + 1}/{W}: {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    tuning = None
+    if autotune:
+        tuning = b.autotune(J, candidates=autotune)
+        print(f"[bench] {name} autotune: {tuning}", file=sys.stderr, flush=True)
     fields = ("n_gates", "updates", "shifts", "nominal_flops", "jacobi_sweeps", "sum_chi3")
     s0 = b.stats()
     torch.cuda.synchronize()
@@ -330,6 +356,7 @@ def run_path(L, h, p, precision, J, K, W, B, match=None):
         "sum_chi3_per_sample": d["sum_chi3"] / B,
         "values": vals.cpu().numpy().reshape(B, n_obs),
         "mean": mean.cpu().numpy(),
+        "autotune": tuning,
     }
     if s_match is not None:
         dm = delta(s0, s_match)
@@ -469,7 +496,7 @@ def hybrid_experiment(L, h, a):
     t0_time = a.t0
     n0 = ti.trotter_steps_for(t0_time)
     pre = ti.config(5).with_(trotter=True, total_time=t0_time, trotter_steps=n0,
-                             n_samples=1, chi_max=16)
+                             n_samples=1, chi_max=a.pre_cap)
     bt = L.Batch(h, L.ProblemStruct(pre), 0, 1, stream=stream)
     torch.cuda.synchronize()
     tp = time.perf_counter()
@@ -482,11 +509,12 @@ def hybrid_experiment(L, h, a):
     shared = bt.read_mps(0)
     prep_stats = bt.stats()
     bt.close()
-    B, J, K, W = a.batch or 768, a.layers_per_step, a.steps, a.warmup
+    B, J, K, W = a.batch or 4096, a.layers_per_step, a.steps, a.warmup
     p = hybrid_segment(B, a.no_pi, shared, a.cycle_caps)
     if (W + K) * J > p.trotter_steps:
         raise SystemExit("warmup + steps exceed the circuit")
-    ps = L.ProblemStruct(p)
+    precision = L.TEPAI_FP32_MIXED if a.hybrid_precision == "mixed" else L.TEPAI_FP64
+    ps = L.ProblemStruct(p, precision=precision)
     b = L.Batch(h, ps, 0, B, stream=stream)
     n_obs = ps.n_obs
     vals = torch.empty(B * n_obs, dtype=torch.float64, device=dev)
@@ -530,12 +558,13 @@ def hybrid_experiment(L, h, a):
         "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": t_timed / K * 1e3,
         "higher_is_better": True,
-        "dtype": "f64",
+        "dtype": ("mixed: c64 storage, f32 MFMA contractions, f64 QR/Jacobi/truncation/estimator"
+                  if precision == L.TEPAI_FP32_MIXED else "f64"),
         "data": "synthetic",
         "variant": "no_pi (biased, Statement 3)" if a.no_pi else "unbiased TE-PAI",
         "config": {"workload": "hybrid: n=100 Heisenberg ring h~U[-1,1]; Trotter segment to "
-                               f"t0={t0_time:g} (N0={n0}, chi=16) on the GPU, then TE-PAI T=2, "
-                               "N=1024, Delta=pi/512, caps " + ("16/32/64 in turn" if a.cycle_caps else "64/32/16 by thirds") + ", Neel start of the segment",
+                               f"t0={t0_time:g} (N0={n0}, chi={a.pre_cap}) on the GPU, then TE-PAI "
+                               "T=2, N=1024, Delta=pi/512, caps " + ("16/32/64 in turn" if a.cycle_caps else "64/32/16 by thirds") + " (a cap below the shared state's bonds truncates its copy), Neel start of the segment",
                    "batch_samples": B, "trotter_steps_per_step": J,
                    "timed_trotter_steps": [W * J, (W + K) * J]},
         "trotter_segment": {"seconds": prep_s, "steps": n0, "updates": int(prep_stats["updates"][0]),
@@ -546,7 +575,7 @@ def hybrid_experiment(L, h, a):
         "series_t_Z0_se_halfZZ_se": series,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "evolve_kernel<2, false> (FP64)",
+                     "kernel": "evolve_kernel<2, %s>" % ("true" if precision == L.TEPAI_FP32_MIXED else "false"),
                      "kernel_ms_per_launch": evolve_ms / K,
                      "flops_per_launch": d["nominal_flops"] / K},
     }
@@ -556,6 +585,51 @@ def hybrid_experiment(L, h, a):
             "from t=0", "from the Neel product state (the oracle does not take the GPU's shared state)")
         line["cpu_baseline"] = cb
     return line
+
+
+def batching_experiment(L, h, a):
+    """The batching configuration at scale: the n = 64 XXZ ring of the
+    throughput workload with bond caps 32, 64 and 128 by sample index mod 3,
+    B samples (default 2048, eight per CU) resident in one batch on the
+    mixed path.  One workgroup runs one sample; the library launches the
+    slots by decreasing cap, and a CU that finishes a small-cap sample takes
+    the next slot, so the hardware scheduler packs the uneven work.  The
+    timed window starts at Trotter step --start-step (96) as in the
+    throughput step; value = B K J / N / t as there."""
+    import tepai_inputs as ti
+    B = a.batch or 2048
+    J, K = a.layers_per_step, a.steps
+    W = max(a.warmup, -(-a.start_step // J))
+    base = ti.config(3)
+    p = base.with_(n_samples=B, chi_per_sample=base.chi_per_sample[:B])
+    if (W + K) * J > p.trotter_steps:
+        raise SystemExit("warmup + steps exceed the circuit")
+    r = run_path(L, h, p, L.TEPAI_FP32_MIXED, J, K, W, B)
+    return {
+        "metric": "TE-PAI MPS samples/s, n=64 XXZ ring, caps 32/64/128 by sample (batching)",
+        "value": r["value"],
+        "unit": "samples/s",
+        "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "dtype": "mixed: c64 storage, f32 MFMA contractions, f64 QR/Jacobi/truncation/estimator",
+        "data": "synthetic",
+        "config": {"workload": "batching: n=64 XXZ ring J_xy=1 J_z=0.5 h~U[-2,2], T=3, N=800, "
+                               "Delta=pi/256, caps (32, 64, 128)[s mod 3], Neel, <Z_i> all i + "
+                               "<Z_0 Z_32>",
+                   "batch_samples": B, "trotter_steps_per_step": J,
+                   "timed_trotter_steps": [W * J, (W + K) * J]},
+        "gates_per_s": r["gates_per_s"],
+        "updates_per_s": r["updates_per_s"],
+        "sum_chi3_per_s": r["sum_chi3_per_s"],
+        "jacobi_sweeps_per_factorisation": r["sweeps"],
+        "sum_chi3_per_sample_in_window": r["sum_chi3_per_sample"],
+        "roofline": {"bound": "alu", "achieved": r["achieved"], "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": r["achieved"] / FP64_PEAK_TFLOPS,
+                     "traffic": None, "kernel": "evolve_kernel<4, true> (mixed)",
+                     "kernel_ms_per_launch": r["kernel_ms_per_launch"],
+                     "flops_per_launch": r["flops_per_launch"]},
+    }
 
 
 def main():
@@ -571,6 +645,12 @@ def main():
         torch.cuda.init()
         from paper_2604_13144_amd import _lib as L
         print(json.dumps(hybrid_experiment(L, L.Handle(0), a)))
+        return
+    if a.workload == "batching":
+        import torch
+        torch.cuda.init()
+        from paper_2604_13144_amd import _lib as L
+        print(json.dumps(batching_experiment(L, L.Handle(0), a)))
         return
     if a.workload == "truncation":
         import torch
@@ -595,12 +675,15 @@ def main():
     Kp = min(K, a.fp64_steps)
     h = L.Handle(0)
     paths = a.paths.split(",")
-    mixed = run_path(L, h, p, L.TEPAI_FP32_MIXED, J, K, W, B, match=Kp) if "mixed" in paths else None
-    plain = run_path(L, h, p, L.TEPAI_FP64, J, Kp, W, B) if "fp64" in paths else None
+    tune = tuple(int(x) for x in a.autotune.split(",") if x) or None
+    mixed = (run_path(L, h, p, L.TEPAI_FP32_MIXED, J, K, W, B, match=Kp, autotune=tune)
+             if "mixed" in paths else None)
+    plain = run_path(L, h, p, L.TEPAI_FP64, J, Kp, W, B, autotune=tune) if "fp64" in paths else None
     if mixed is None or plain is None:
         # one path only (profiling runs): report it alone
         r = mixed or plain
         print(json.dumps({"path": "mixed" if mixed else "fp64", "value": r["value"], "unit": "samples/s",
+                          "autotune": r["autotune"],
                           "kernel_ms_per_launch": r["kernel_ms_per_launch"],
                           "flops_per_launch": r["flops_per_launch"],
                           "achieved_tflops": r["achieved"],
@@ -636,6 +719,8 @@ def main():
         "sum_chi3_per_s": mixed["sum_chi3_per_s"],
         "mean_max_bond": mixed["mean_max_bond"],
         "jacobi_sweeps_per_factorisation": mixed["sweeps"],
+        "autotune": ({"mixed": mixed["autotune"], "fp64": plain["autotune"]}
+                     if mixed["autotune"] else None),
         "plain_fp64": {"value": plain["value"], "unit": "samples/s", "dtype": "c128 (f64)",
                        "steps": Kp, "timed_trotter_steps": [W * J, (W + Kp) * J],
                        "ms_per_step": plain["ms_per_step"], "gates_per_s": plain["gates_per_s"],

@@ -149,9 +149,15 @@ typedef struct {
  * right-canonical (not checked: truncations are optimal only in that form;
  * nor are the values checked: a non-finite entry makes every sample
  * non-finite, which tepai_run reports as TEPAI_ENUMERIC).
- * bond[0] = bond[n] = 1, and no bond may exceed the smallest bond cap of the
- * samples.  Caller-owned; the library copies it in tepai_batch_create (and
- * tepai_run) and keeps no pointer. */
+ * bond[0] = bond[n] = 1, and no bond may exceed chi_max.  A sample whose
+ * cap is below the state's largest bond starts from a truncated copy
+ * (truncation on copy, done in tepai_batch_create): the copy's centre is
+ * moved to site 0 by exact single-site SVD shifts, then swept to site n-1,
+ * each shift keeping min(cap, #{sigma_i > svd_cutoff * sigma_0}) singular
+ * values renormalised to unit norm, so every cut is truncated optimally for
+ * the state the earlier cuts left; these shifts count in the sample's
+ * `shifts`, and its centre starts at site n-1.  Caller-owned; the library
+ * copies it in tepai_batch_create (and tepai_run) and keeps no pointer. */
 typedef struct {
   const uint32_t* bond;         /* [n_qubits + 1] */
   const double* tensors;        /* sum_k 2 bond[k] bond[k+1] complex values */
@@ -289,6 +295,25 @@ tepai_status tepai_batch_read_mps(tepai_batch* b, uint32_t slot, uint64_t capaci
                                   uint32_t* bond, uint32_t* qubit_at, uint32_t* centre,
                                   uint64_t* n_values, double* tensors);
 void tepai_batch_destroy(tepai_batch* b);
+
+/* Autotuning of the one SVD tile parameter that the matrix size does not
+ * fix: the panel width of the pivoted-QR preconditioner (QR steps between
+ * two applications of the accumulated reflectors to the trailing columns;
+ * 1..32, 32 by default).  From the batch's current state, each of the
+ * n_candidates widths runs the next n_layers Trotter steps, timed with HIP
+ * events on the batch's stream, after which the whole workspace is restored
+ * from d_scratch (a device buffer of at least the batch's workspace size,
+ * tepai_workspace_size for its count), so the batch ends where it started
+ * and later steps are computed as if untuned, up to the rounding of the
+ * chosen width.  The batch keeps the width with the highest nominal-flop
+ * rate (eq. Wsample's cost model over the same steps) for its later steps;
+ * *chosen reports it, and ms[i], flops[i] (each may be NULL) each
+ * candidate's time and nominal flops.  Synchronises the stream.  Results
+ * are equally valid for every width (the SVD does not depend on it beyond
+ * rounding). */
+tepai_status tepai_batch_autotune(tepai_batch* b, uint32_t n_layers, const uint32_t* candidates,
+                                  uint32_t n_candidates, void* d_scratch, size_t scratch_bytes,
+                                  double* ms, double* flops, uint32_t* chosen);
 
 /* A captured read-out step of a batch: the launches of tepai_batch_evolve
  * (n_layers Trotter steps), tepai_batch_observe into d_values / d_weights

@@ -153,6 +153,31 @@ class MPS:
         self.centre = c + d
         self.stats.shifts += 1
 
+    def truncate_to(self, chi: int):
+        """Bring every bond to at most chi: the copy of a shared start for a
+        sample whose cap is below the start's largest bond (the hybrid start
+        of sec. "Implementation" leaves the cap of the shared state open).
+        The centre moves to the first site by the exact shifts above, then
+        sweeps to the last site; each step factorises the centre site as a
+        (2 chi_l) x chi_r matrix, keeps k = min(chi, #{sigma > cutoff
+        sigma_0}) singular values renormalised to unit norm, and moves the
+        centre one site right.  With the rest of the chain right-canonical,
+        step c is the optimal rank-k truncation, across the cut after site c,
+        of the state that the earlier steps left.  Every step counts as a
+        shift."""
+        while self.centre > 0:
+            self.shift(self.centre, -1)
+        for c in range(self.n - 1):
+            A = self.A[c]
+            cl, _, cr = A.shape
+            U, S, Vh = self._svd(A.reshape(cl * 2, cr))
+            k = min(chi, max(self._keep(S), 1))
+            Sk = S[:k] / np.linalg.norm(S[:k])
+            self.A[c] = U[:, :k].reshape(cl, 2, k)
+            self.A[c + 1] = np.einsum("kb,bsc->ksc", Sk[:, None] * Vh[:k], self.A[c + 1])
+            self.centre = c + 1
+            self.stats.shifts += 1
+
     # -- two-site ---------------------------------------------------------
     def update(self, i: int, G: np.ndarray, chi: int, right: bool):
         assert self.centre in (i, i + 1)
@@ -197,6 +222,8 @@ class MPS:
                 self.update(op[1], op[2], op[3], op[4])
             elif kind == "shift":
                 self.shift(op[1], op[2])
+            elif kind == "truncate":
+                self.truncate_to(op[1])
             else:
                 raise ValueError(kind)
         return self

@@ -41,6 +41,9 @@ Operations are expressed on sites:
                                      s_i * 2 + s_{i+1}; right=True leaves the
                                      centre on i+1
     ("shift",  c, +1 | -1)           move the centre from site c to c +/- 1
+    ("truncate", chi)                first op of a sample that starts from a
+                                     shared state with a bond above its cap
+                                     chi (``MPS.truncate_to``)
 """
 from __future__ import annotations
 
@@ -116,6 +119,11 @@ def build_schedule(problem, table, circuit, chi: Optional[int] = None) -> Tuple[
         site_of[q] = k
     ops: List[tuple] = []
     centre = [init.centre if init is not None else 0]
+    if init is not None and max(t.shape[2] for t in init.tensors) > chi:
+        # a shared start with a bond above this sample's cap is truncated on
+        # copy, which leaves the centre on the last site
+        ops.append(("truncate", chi))
+        centre[0] = n - 1
 
     def move_centre_to(i: int):
         # the centre must end on i or i + 1

@@ -100,6 +100,8 @@ PROTOTYPES = {
     "tepai_run": (C.c_int, [_P, C.POINTER(tepai_problem), C.c_uint32, _P, _P, _P, _P,
                             C.POINTER(tepai_sample_stats)]),
     "tepai_batch_capture_step": (C.c_int, [_P, C.c_uint32, _P, _P, _P, _P, C.POINTER(_P)]),
+    "tepai_batch_autotune": (C.c_int, [_P, C.c_uint32, _P, C.c_uint32, _P, C.c_size_t, _P, _P,
+                                       C.POINTER(C.c_uint32)]),
     "tepai_step_graph_launch": (C.c_int, [_P]),
     "tepai_step_graph_destroy": (None, [_P]),
     "tepai_run_noalloc": (C.c_int, [_P, C.POINTER(tepai_problem), _P, _P, _P, _P, _P,
@@ -365,6 +367,24 @@ class Batch:
             tensors.append(vals[at:at + 2 * a * c].reshape(a, 2, c).copy())
             at += 2 * a * c
         return MPSState(tuple(tensors), int(centre.value), tuple(int(q) for q in qubit_at))
+
+    def autotune(self, n_layers, candidates=(8, 16, 24, 32), scratch=None) -> dict:
+        """Time the QR panel widths over the next n_layers steps (state
+        restored after each) and keep the fastest; returns the timings."""
+        import torch
+        if scratch is None:
+            scratch = torch.empty(self.workspace.numel(), dtype=torch.uint8,
+                                  device=self.workspace.device)
+        cand = np.asarray(candidates, dtype=np.uint32)
+        ms = np.zeros(len(cand))
+        fl = np.zeros(len(cand))
+        chosen = C.c_uint32()
+        _check(load().tepai_batch_autotune(self.b, n_layers, cand.ctypes.data, len(cand),
+                                           C.c_void_p(scratch.data_ptr()), scratch.numel(),
+                                           ms.ctypes.data, fl.ctypes.data, C.byref(chosen)),
+               self.h.h)
+        return {"chosen": int(chosen.value), "candidates": [int(c) for c in cand],
+                "ms": ms.tolist(), "nominal_flops": fl.tolist()}
 
     def capture_step(self, n_layers, d_values, d_weights, d_mean, d_se) -> "StepGraph":
         """Record evolve(n_layers) + observe + reduce once as a HIP graph."""

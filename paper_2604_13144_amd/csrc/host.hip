@@ -223,12 +223,9 @@ tepai_status validate(tepai_handle* h, const tepai_problem* p) {
   if (const tepai_mps* m = p->initial_mps) {
     if (!m->bond || !m->tensors) return fail(h, TEPAI_EINVAL, "initial_mps bond/tensors NULL");
     if (m->bond[0] != 1 || m->bond[n] != 1) return fail(h, TEPAI_EINVAL, "initial_mps end bonds must be 1");
-    uint32_t cap = p->chi_max;
-    if (p->chi_per_sample)
-      for (uint64_t s = 0; s < p->n_samples; ++s) cap = std::min(cap, p->chi_per_sample[s]);
     for (uint32_t k = 0; k <= n; ++k)
-      if (m->bond[k] < 1 || m->bond[k] > cap)
-        return fail(h, TEPAI_ERANGE, "initial_mps bond " + std::to_string(k) + " outside [1, smallest bond cap]");
+      if (m->bond[k] < 1 || m->bond[k] > p->chi_max)
+        return fail(h, TEPAI_ERANGE, "initial_mps bond " + std::to_string(k) + " outside [1, chi_max]");
     if (m->centre >= n) return fail(h, TEPAI_ERANGE, "initial_mps centre out of range");
     if (m->qubit_at) {
       std::vector<int> seen(n, 0);
@@ -306,6 +303,8 @@ struct tepai_batch {
   tepai_handle* h;
   hipStream_t stream;
   EngineArgs args;
+  void* ws;           // the caller's workspace and the bytes the batch uses of it
+  size_t ws_bytes;
   uint32_t trotter_steps;
   uint32_t layers_done;
   uint32_t n_obs;
@@ -537,6 +536,8 @@ tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_
   auto* b = new tepai_batch;
   b->h = h;
   b->stream = (hipStream_t)hip_stream;
+  b->ws = workspace;
+  b->ws_bytes = lay.total;
   b->trotter_steps = p->trotter_steps;
   b->layers_done = 0;
   b->n_obs = p->n_obs;
@@ -590,6 +591,7 @@ tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_
   a.stop_tan = a.mixed ? kStopTanMixed : kStopTanFp64;
   a.skip_tol = a.mixed ? kSkipMixed : kSkipFp64;
   a.per_gate = (p->flags & TEPAI_PER_GATE) ? 1u : 0u;
+  a.qr_panel = 32;
   a.log_g1_step = t.log_step;
   a.l_eff = L;
   a.n = p->n_qubits;
@@ -602,6 +604,7 @@ tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_
   a.init_bond = nullptr;
   a.init_qubit = nullptr;
   a.init_centre = 0;
+  a.init_max_bond = 0;
   const uint32_t n = p->n_qubits;
   if (const tepai_mps* m = p->initial_mps) {
     // stage the shared MPS in the batch (the caller's buffers are not kept)
@@ -626,6 +629,7 @@ tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_
     base += align256(sizeof(uint16_t) * n);
     a.init_tensors = (const double2*)base;
     a.init_centre = m->centre;
+    a.init_max_bond = *std::max_element(m->bond, m->bond + n + 1);
   }
   hipError_t e = hipMemcpyAsync(ws + lay.rows, b->rows.data(), sizeof(DevRow) * L, hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess)
@@ -644,6 +648,10 @@ tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_
       e = hipMemcpyAsync((void*)a.init_tensors, b->init_tensors.data(), sizeof(double2) * b->init_tensors.size(), hipMemcpyHostToDevice, b->stream);
   }
   if (e == hipSuccess) e = launch_init(a, b->stream);
+  // truncation on copy, for slots whose cap is below the shared start's bonds
+  bool truncate = false;
+  for (uint32_t i = 0; i < count; ++i) truncate = truncate || b->caps[i] < a.init_max_bond;
+  if (e == hipSuccess && truncate) e = launch_start(a, b->stream);
   if (e != hipSuccess) {
     delete b;
     return fail(h, TEPAI_EDEVICE, std::string("batch set-up: ") + hipGetErrorString(e));
@@ -742,6 +750,74 @@ tepai_status tepai_batch_read_mps(tepai_batch* b, uint32_t slot, uint64_t capaci
 }
 
 void tepai_batch_destroy(tepai_batch* b) { delete b; }
+
+tepai_status tepai_batch_autotune(tepai_batch* b, uint32_t n_layers, const uint32_t* candidates,
+                                  uint32_t n_candidates, void* d_scratch, size_t scratch_bytes,
+                                  double* ms, double* flops, uint32_t* chosen) {
+  if (!b || !candidates || !chosen || n_candidates == 0) return TEPAI_EINVAL;
+  if (n_layers == 0) return fail(b->h, TEPAI_ERANGE, "n_layers must be >= 1");
+  for (uint32_t i = 0; i < n_candidates; ++i)
+    if (candidates[i] < 1 || candidates[i] > 32)
+      return fail(b->h, TEPAI_ERANGE, "QR panel widths are 1..32");
+  if ((uint64_t)b->layers_done + n_layers > b->trotter_steps)
+    return fail(b->h, TEPAI_ERANGE, "tuning steps beyond the last Trotter step");
+  if (!d_scratch || scratch_bytes < b->ws_bytes)
+    return fail(b->h, TEPAI_ENOMEM, "scratch smaller than the batch's workspace");
+  TEPAI_HIP(b->h, hipSetDevice(b->h->device));
+  const uint32_t count = b->args.count;
+  std::vector<SampleState> st(count);
+  auto work = [&](double* out) -> hipError_t {   // summed nominal flops of the batch
+    hipError_t e = hipMemcpyAsync(st.data(), b->args.states, sizeof(SampleState) * count,
+                                  hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    double f = 0.0;
+    for (const SampleState& s : st) f += s.nominal_flops;
+    *out = f;
+    return e;
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_scratch, b->ws, b->ws_bytes, hipMemcpyDeviceToDevice, b->stream);
+  double f0 = 0.0;
+  if (e == hipSuccess) e = work(&f0);
+  const uint32_t before = b->args.qr_panel;
+  uint32_t best = before;
+  double best_rate = -1.0;
+  for (uint32_t i = 0; i < n_candidates && e == hipSuccess; ++i) {
+    b->args.qr_panel = candidates[i];
+    e = hipEventRecord(e0, b->stream);
+    if (e == hipSuccess) e = launch_evolve(b->args, n_layers, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    double f1 = 0.0;
+    if (e == hipSuccess) e = work(&f1);
+    // back to the state before the candidate ran
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b->ws, d_scratch, b->ws_bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) break;
+    if (ms) ms[i] = t;
+    if (flops) flops[i] = f1 - f0;
+    const double rate = t > 0.0f ? (f1 - f0) / t : 0.0;
+    if (rate > best_rate) {
+      best_rate = rate;
+      best = candidates[i];
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) {
+    b->args.qr_panel = before;
+    return fail(b->h, TEPAI_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+  }
+  b->args.qr_panel = best;
+  *chosen = best;
+  return TEPAI_OK;
+}
 
 }  // extern "C"
 

@@ -275,6 +275,7 @@ struct Shared {
   int n_c;
   uint32_t max_bond;
   uint32_t sflags;       // TEPAI_SAMPLE_* bits
+  int qr_panel;          // QR steps per panel (1..32; the autotuned parameter)
 };
 
 struct Slot {
@@ -879,7 +880,8 @@ __device__ __noinline__ void qrcp(z2* Z_, int nr, int nc, Shared& sh, z2* Ul_, z
   const int l16 = threadIdx.x & 15, row = threadIdx.x >> 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int m = nr < nc ? nr : nc;
-  const int nbmax = (jl_size<RPL>() / nr) < 32 ? (jl_size<RPL>() / nr) : 32;
+  const int pw = sh.qr_panel < 32 ? sh.qr_panel : 32;
+  const int nbmax = (jl_size<RPL>() / nr) < pw ? (jl_size<RPL>() / nr) : pw;
 
   // exact squared norms of rows r0.. of columns r0.. (all rows read, in-bounds)
   auto exact_norms = [&](int r0) {
@@ -1292,8 +1294,10 @@ __device__ void apply_local(const Slot& S, int k, const z2 U[4], Shared& sh) {
 }
 
 // Move the centre from site c to c+1 (SVD of A_c as a (2 cl) x cr matrix).
+// cap > 0 also keeps at most cap singular values and renormalises the kept
+// ones (the truncation sweep of a shared start).
 template <int RPL, bool MIX>
-__device__ void shift_right(const Slot& S, int c, double cutoff, Shared& sh) {
+__device__ void shift_right(const Slot& S, int c, double cutoff, Shared& sh, int cap = 0) {
   using TS = TSite<MIX>;
   TS* A = site<TS>(S, c);
   TS* B = site<TS>(S, c + 1);
@@ -1304,8 +1308,10 @@ __device__ void shift_right(const Slot& S, int c, double cutoff, Shared& sh) {
     S.Y0[(uint64_t)col * R + row] = toz(A[idx]);
   }
   sync_block();
-  const Factor f = factorise<RPL, MIX>(S.W, S.Y0, S.P, R, C, C, cutoff, false, sh, S.Jl, S.stop, S.skip);
+  const Factor f = factorise<RPL, MIX>(S.W, S.Y0, S.P, R, C, cap > 0 ? cap : C, cutoff, false, sh,
+                                       S.Jl, S.stop, S.skip);
   const int k = f.k;
+  const double sc = cap > 0 ? f.scale : 1.0;
   project<MIX>(S.W, S.Y0, S.P, R, C, k, sh);
   for (int idx = threadIdx.x; idx < R * k; idx += NT) {
     const int row = idx / k, j = idx - row * k;
@@ -1324,7 +1330,7 @@ __device__ void shift_right(const Slot& S, int c, double cutoff, Shared& sh) {
           [&](int j, int col, z2 v) { ww[(uint64_t)j * nb + col] = v; });
   }
   sync_block();
-  for (int idx = threadIdx.x; idx < k * nb; idx += NT) B[idx] = fromz<TS>(S.W[idx]);
+  for (int idx = threadIdx.x; idx < k * nb; idx += NT) B[idx] = fromz<TS>(cscale(S.W[idx], sc));
   if (threadIdx.x == 0) {
     sh.bond[c + 1] = (uint16_t)k;
     sh.centre = c + 1;
@@ -1651,6 +1657,7 @@ __device__ void load_state(const EngineArgs& a, int slot, Shared& sh) {
     sh.max_bond = st->max_bond;
     sh.n_c = st->sign < 0 ? 1 : 0;
     sh.sflags = st->flags;
+    sh.qr_panel = a.qr_panel >= 1 ? (int)a.qr_panel : 32;
     sh.p_active = 0;
   }
   sync_block();
@@ -1743,6 +1750,31 @@ __global__ __launch_bounds__(NT) void init_kernel(EngineArgs a) {
     st->sum_chi3 = st->nominal_flops = st->discarded = st->max_discarded = 0.0;
     st->min_gap = INFINITY;
   }
+}
+
+// Truncation on copy: a slot whose cap is below the shared start's largest
+// bond brings its copy to the cap before any step: the centre moves to the
+// first site by exact shifts, then sweeps to the last site, each shift
+// keeping at most cap singular values, renormalised (the state each step
+// leaves is truncated optimally across the next cut).  Other slots return
+// at once.
+template <int RPL, bool MIX>
+__global__ __launch_bounds__(NT) void start_kernel(EngineArgs a) {
+  __shared__ Shared sh;
+  __shared__ z2 Jl[jl_size<RPL>()];
+  const int slot = (int)a.launch_order[blockIdx.x];
+  if (a.chi_caps[slot] >= a.init_max_bond) return;    // the whole workgroup
+  const Slot S = make_slot<MIX>(a, slot, Jl);
+  load_state(a, slot, sh);
+  while (sh.centre > 0) shift_left<RPL, MIX>(S, sh.centre, S.cutoff, sh);
+  for (int c = 0; c + 1 < (int)a.n; ++c) shift_right<RPL, MIX>(S, c, S.cutoff, sh, (int)S.chi);
+  if (threadIdx.x == 0) {     // the copy's largest bond, no longer the shared state's
+    uint32_t mb = 1;
+    for (int k = 0; k <= (int)a.n; ++k) mb = sh.bond[k] > mb ? sh.bond[k] : mb;
+    sh.max_bond = mb;
+  }
+  sync_block();
+  store_state(a, slot, sh, 0);
 }
 
 template <int RPL, bool MIX>
@@ -2118,6 +2150,25 @@ static void observe_rpl(const EngineArgs& a, double* v, double* w, hipStream_t s
     case 4: hipLaunchKernelGGL((observe_kernel<4, MIX>), dim3(a.count), dim3(NT), 0, s, a, v, w); break;
     default: hipLaunchKernelGGL((observe_kernel<8, MIX>), dim3(a.count), dim3(NT), 0, s, a, v, w); break;
   }
+}
+
+template <bool MIX>
+static void start_rpl(const EngineArgs& a, hipStream_t s) {
+  switch (rows_per_lane(a.chi_max)) {
+    case 1: hipLaunchKernelGGL((start_kernel<1, MIX>), dim3(a.count), dim3(NT), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((start_kernel<2, MIX>), dim3(a.count), dim3(NT), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((start_kernel<4, MIX>), dim3(a.count), dim3(NT), 0, s, a); break;
+    default: hipLaunchKernelGGL((start_kernel<8, MIX>), dim3(a.count), dim3(NT), 0, s, a); break;
+  }
+}
+
+hipError_t launch_start(const EngineArgs& a, hipStream_t s) {
+  (void)hipGetLastError();
+  if (a.mixed)
+    start_rpl<true>(a, s);
+  else
+    start_rpl<false>(a, s);
+  return hipGetLastError();
 }
 
 hipError_t launch_observe(const EngineArgs& a, double* d_values, double* d_weights,

@@ -86,10 +86,13 @@ struct EngineArgs {
   const uint32_t* init_bond;     // [n + 1]
   const uint16_t* init_qubit;    // [n]
   uint32_t init_centre;
+  uint32_t init_max_bond;        // largest bond of the shared start (0: none)
+  uint32_t qr_panel;             // QR steps per panel of lazy trailing updates (1..32)
 };
 
 // Kernel launchers (kernels.hip).
 hipError_t launch_init(const EngineArgs& a, hipStream_t s);
+hipError_t launch_start(const EngineArgs& a, hipStream_t s);
 hipError_t launch_evolve(const EngineArgs& a, uint32_t n_layers, hipStream_t s);
 hipError_t launch_observe(const EngineArgs& a, double* d_values, double* d_weights, hipStream_t s);
 hipError_t launch_reduce(uint64_t count, uint32_t n_obs, const double* v, const double* w,

@@ -186,9 +186,11 @@ def test_initial_mps_validation_and_workspace():
     extra = L.tepai_workspace_size(None, L.ProblemStruct(p), 1) - \
         L.tepai_workspace_size(None, L.ProblemStruct(p.with_(initial_mps=None)), 1)
     assert extra >= 16 * sum(a.size for a in init.tensors)
-    # a bond above the smallest cap of the samples
+    # a bond above a sample's cap is allowed (that sample truncates its copy),
+    # one above chi_max is not
+    L.tepai_validate(None, L.ProblemStruct(p.with_(chi_per_sample=(4, 2, 4))))
     with pytest.raises(L.TepaiError) as e:
-        L.tepai_validate(None, L.ProblemStruct(p.with_(chi_per_sample=(4, 2, 4))))
+        L.tepai_validate(None, L.ProblemStruct(p.with_(chi_max=2, chi_per_sample=None)))
     assert e.value.status == -2
     # not a permutation
     bad = ti.InitialMPS(init.tensors, init.centre, (0,) * 6)

@@ -109,3 +109,58 @@ def test_gpu_only_hybrid_matches_oracle_hybrid(handle):
     vals, wts, st = gpu_batch(handle, seg.with_(initial_mps=m), 0, 5, [6])
     # the oracle runs the same segment from its own Trotter state
     compare(seg.with_(initial_mps=trotter_initial_mps(pre, 10, 10)), range(5), vals, wts, st, 0)
+
+
+# --- truncation on copy: a shared start whose bonds exceed some samples' caps
+
+def centred_random_start(n, chi, seed, centre):
+    from oracle.mps import MPS
+    init = ti.random_mps(n, chi, seed)
+    m = MPS.from_initial(init)
+    while m.centre < centre:
+        m.shift(m.centre, +1)
+    return ti.InitialMPS(tensors=tuple(m.A), centre=centre, qubit_at=init.qubit_at)
+
+
+def truncated_start_problem():
+    # bonds up to 16 around the middle of a 12-site chain; caps 4, 8, 16, 6, 2:
+    # four of the five samples truncate their copy before the first step
+    init = centred_random_start(12, 16, seed=9, centre=5)
+    p = ti.small_ring(12, seed=4, T=0.3, N=6, delta=math.pi / 16, chi=16, n_samples=5)
+    return p.with_(initial_mps=init, chi_per_sample=(4, 8, 16, 6, 2)), init
+
+
+def test_truncation_on_copy_fp64(handle):
+    p, init = truncated_start_problem()
+    assert max(init.bonds()) == 16
+    print("truncation on copy fp64: random chi=16 start, caps 4/8/16/6/2", flush=True)
+    vals, wts, st = gpu_batch(handle, p, 0, p.n_samples, [1, 5])
+    assert all(int(m) <= c for m, c in zip(st["max_bond"], p.chi_per_sample))
+    compare(p, range(p.n_samples), vals, wts, st, 0)
+
+
+def test_truncation_on_copy_state_before_any_step(handle):
+    # right after batch creation a truncated slot holds the oracle's truncated
+    # copy, centre on the last site; the cap-16 slot holds the start unchanged
+    from oracle.mps import MPS
+    p, init = truncated_start_problem()
+    b = L.Batch(handle, L.ProblemStruct(p), 0, p.n_samples)
+    for slot, cap in enumerate(p.chi_per_sample):
+        g = b.read_mps(slot)
+        ref = MPS.from_initial(init, p.svd_cutoff)
+        if cap < 16:
+            ref.truncate_to(cap)
+        assert g.centre == ref.centre and g.bonds() == tuple(ref.bonds())
+        dg = MPS.from_initial(g).to_dense()
+        assert np.max(np.abs(dg - ref.to_dense())) <= 1e-12, slot
+    st = b.stats()
+    assert list(st["shifts"]) == [5 + 11 if c < 16 else 0 for c in p.chi_per_sample]
+    assert list(st["max_bond"]) == [min(c, 16) for c in p.chi_per_sample]
+    b.close()
+
+
+def test_truncation_on_copy_mixed(handle):
+    p, _ = truncated_start_problem()
+    print("truncation on copy mixed: random chi=16 start, caps 4/8/16/6/2", flush=True)
+    vals, _, st = run_batch(handle, p, p.n_samples, [6], L.TEPAI_FP32_MIXED)
+    print("truncation on copy mixed worst", against_oracle(p, vals, st))

@@ -76,3 +76,58 @@ def test_hybrid_estimator_is_unbiased_for_the_whole_evolution():
     r = run(seg)
     for o, obs in enumerate(seg.observables):
         assert abs(r.mean[o] - dense.expectation(psi, obs)) < 5 * r.std_err[o]
+
+
+# ------------------------------------------------ truncation on copy
+def centred(init, c):
+    """The same state with its orthogonality centre moved to site c."""
+    from oracle.mps import MPS
+    m = MPS.from_initial(init)
+    while m.centre < c:
+        m.shift(m.centre, +1)
+    return ti.InitialMPS(tensors=tuple(m.A), centre=c, qubit_at=init.qubit_at)
+
+
+def dense_truncation_sweep(psi, n, chi, cutoff=1e-12):
+    """The definition written out on the state vector: the optimal rank-k cut
+    (k = min(chi, #{sigma > cutoff sigma_0}), renormalised) after site 0,
+    then after site 1 of the state that cut left, and so on."""
+    for c in range(n - 1):
+        U, S, Vh = np.linalg.svd(psi.reshape(2 ** (c + 1), -1), full_matrices=False)
+        k = min(chi, max(int(np.count_nonzero(S > cutoff * S[0])), 1))
+        psi = ((U[:, :k] * (S[:k] / np.linalg.norm(S[:k]))) @ Vh[:k]).reshape(-1)
+    return psi
+
+
+def test_truncation_on_copy_equals_the_dense_sweep():
+    from oracle.mps import MPS
+    init = centred(ti.random_mps(7, 8, seed=5), 3)
+    m0 = MPS.from_initial(init)
+    psi0 = m0.to_dense()
+    assert max(m0.bonds()) == 8
+    for chi in (1, 2, 3, 5):
+        m = MPS.from_initial(init)
+        m.truncate_to(chi)
+        assert max(m.bonds()) <= chi and m.centre == 6
+        ref = dense_truncation_sweep(psi0, 7, chi)
+        assert np.max(np.abs(m.to_dense() - ref)) <= 1e-12, chi
+        assert abs(np.linalg.norm(m.to_dense()) - 1.0) <= 1e-13
+        for A in m.A[:-1]:      # sites left of the centre are left-canonical
+            X = A.reshape(-1, A.shape[2])
+            assert np.allclose(X.conj().T @ X, np.eye(X.shape[1]), atol=1e-12)
+        assert m.stats.shifts == 3 + 6     # exact shifts to site 0, then the sweep
+
+
+def test_truncation_on_copy_only_below_the_largest_bond():
+    # a sample whose cap holds the shared state starts from it unchanged;
+    # one with a smaller cap starts with the truncation sweep
+    init = centred(ti.random_mps(7, 8, seed=5), 3)
+    p = ti.small_ring(7, seed=2, T=0.2, N=2, delta=math.pi / 16, chi=8, n_samples=3,
+                      periodic=False).with_(initial_mps=init, chi_per_sample=(8, 4, 2))
+    t = pai.build_table(p)
+    from oracle.schedule import build_schedule
+    for s, chi in enumerate((8, 4, 2)):
+        ops, _ = build_schedule(p, t, sampler.sample_circuit(p, t, s), chi)
+        assert (ops[0] == ("truncate", chi)) == (chi < 8)
+        r = run_sample(p, t, s)
+        assert max(r.bonds) <= chi

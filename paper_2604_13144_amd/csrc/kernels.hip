@@ -397,7 +397,8 @@ constexpr double kNormRecompute = 0.25;
 // LDS and stay zero), so the element loop is straight-line code that the
 // compiler can interleave.  Rows that are inactive or
 // already orthogonal to tolerance leave both columns untouched.  Returns
-// the cosine |x^H y| / (|x||y|) of the pair before the rotation, or -1 when
+// the squared cosine |x^H y|^2 / (|x|^2 |y|^2) of the pair before the
+// rotation (no division or square root on the rotation's path), or -1 when
 // this row did not rotate.
 template <int E>
 __device__ __forceinline__ double rotate_rows(z2 (&x)[E], double& al, lz2* y, ld* yn, int l16,
@@ -419,7 +420,7 @@ __device__ __forceinline__ double rotate_rows(z2 (&x)[E], double& al, lz2* y, ld
   double tabs = -1.0;
   if (rot) {
     const Rot r = rot_params(al, be, gr, gi, g2);
-    tabs = sqrt(g2 / (al * be));
+    tabs = g2 * rcp_nr(al * be);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       rot_apply(r, x[e], yv[e]);
@@ -470,7 +471,7 @@ __device__ __forceinline__ double rotate_split(lz2* xp, lz2* yq, ld* pn, ld* qn,
   double tabs = -1.0;
   if (rot) {
     const Rot r = rot_params(al, be, gr, gi, g2);
-    tabs = sqrt(g2 / (al * be));
+    tabs = g2 * rcp_nr(al * be);
 #pragma unroll
     for (int e = 0; e < EG; ++e) {
       rot_apply(r, xv[e], yv[e]);
@@ -586,7 +587,7 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_, do
       sh.tmax = 0.0;
     }
     sync_block();
-    double tmx = -1.0;     // largest cosine of the pairs this thread's row rotated
+    double tmx = -1.0;     // largest squared cosine of the pairs this thread's row rotated
 #pragma unroll 1
     for (int I = 0; I < nb; ++I) {
       const int pi = I * JB + row;                       // position of this row's column
@@ -694,7 +695,7 @@ __device__ __noinline__ int jacobi(z2* W_, int R, int C, Shared& sh, z2* Jl_, do
     const int rotated = sh.flag;
     const double tm = sh.tmax;
     sync_block();
-    if (!rotated || tm <= stop) return sweep;
+    if (!rotated || tm <= stop * stop) return sweep;
   }
   return -1;
 }

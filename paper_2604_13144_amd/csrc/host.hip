@@ -588,7 +588,7 @@ tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_
   // complex64 contractions leave rounding noise near 1e-8 sigma_0 in the
   // spectrum; the mixed path does not count it as Schmidt rank
   a.cutoff = a.mixed ? std::max(p->svd_cutoff, kCutoffMixed) : p->svd_cutoff;
-  a.stop_tan = a.mixed ? kStopTanMixed : kStopTanFp64;
+  a.stop_cos = a.mixed ? kStopCosMixed : kStopCosFp64;
   a.skip_tol = a.mixed ? kSkipMixed : kSkipFp64;
   a.per_gate = (p->flags & TEPAI_PER_GATE) ? 1u : 0u;
   a.qr_panel = 32;

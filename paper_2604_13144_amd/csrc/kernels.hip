@@ -1700,7 +1700,7 @@ __device__ Slot make_slot(const EngineArgs& a, int slot, z2* Jl) {
   S.W = S.Y0 + q;
   S.P = S.W + q;
   S.cutoff = a.cutoff;
-  S.stop = a.stop_tan;
+  S.stop = a.stop_cos;
   S.skip = a.skip_tol;
   S.chi = a.states[slot].chi_cap;
   S.n = a.n;

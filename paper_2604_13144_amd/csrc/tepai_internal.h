@@ -16,8 +16,8 @@ constexpr int kMaxRows = 4096;        // PAI table rows per Trotter step
 constexpr int kMaxStringOps = 8;
 constexpr int kThreads = 512;         // engine block: eight wave64 wavefronts
 constexpr int kMaxSweeps = 60;           // Jacobi sweep cap per factorisation
-constexpr double kStopTanFp64 = 1e-8;    // FP64 path: residual ~1e-16
-constexpr double kStopTanMixed = 1e-5;   // mixed path: residual ~1e-10
+constexpr double kStopCosFp64 = 1e-8;    // FP64 path: residual ~1e-16
+constexpr double kStopCosMixed = 1e-5;   // mixed path: residual ~1e-10
 constexpr double kCutoffMixed = 1e-7;    // mixed path: relative singular-value floor
 constexpr double kSkipFp64 = 0x1p-53;    // FP64 path: Jacobi pair threshold u sqrt(R)
 constexpr double kSkipMixed = 1e-15;     // mixed path: inputs carry ~1e-7 errors anyway
@@ -69,7 +69,7 @@ struct EngineArgs {
   uint64_t first_sample;  // global index of slot 0
   uint64_t seed;
   double cutoff;
-  double stop_tan;        // Jacobi stop: a sweep whose rotations all have |tan| <= this
+  double stop_cos;        // Jacobi stop: a sweep whose rotated pairs all had cosine <= this
   double skip_tol;        // Jacobi skips a pair with |x^H y| <= skip_tol sqrt(R) |x||y|
   double log_g1_step;
   uint32_t l_eff;

@@ -224,3 +224,20 @@ def test_sample_flag_bits_are_the_headers():
     assert re.search(r"TEPAI_SAMPLE_NONFINITE\s*=\s*1u", src)
     assert re.search(r"TEPAI_SAMPLE_NONCONVERGED\s*=\s*2u", src)
     assert (L.TEPAI_SAMPLE_NONFINITE, L.TEPAI_SAMPLE_NONCONVERGED) == (1, 2)
+
+
+def test_null_handles_and_batches_are_rejected_on_the_host():
+    """The entry points that take a batch, a graph or a handle refuse NULL
+    with TEPAI_EINVAL before any device work (no GPU needed)."""
+    import ctypes as C
+    lib = L.load()
+    p = ti.small_ring(6, seed=1, n_samples=2)
+    ps = L.ProblemStruct(p)
+    cand = (C.c_uint32 * 1)(8)
+    chosen = C.c_uint32()
+    assert lib.tepai_batch_autotune(None, 1, cand, 1, None, 0, None, None, C.byref(chosen)) == -1
+    g = C.c_void_p()
+    assert lib.tepai_batch_capture_step(None, 1, None, None, None, None, C.byref(g)) == -1
+    assert lib.tepai_step_graph_launch(None) == -1
+    lib.tepai_step_graph_destroy(None)          # a no-op
+    assert lib.tepai_run_noalloc(None, ps.ref(), None, None, None, None, None, None) == -1

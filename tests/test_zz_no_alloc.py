@@ -26,8 +26,8 @@ def handle():
     return L.Handle(0)
 
 
-def run_noalloc(handle, p):
-    ps = L.ProblemStruct(p)
+def run_noalloc(handle, p, precision=0):
+    ps = L.ProblemStruct(p, precision=precision)
     dev = torch.device("cuda", 0)
     ns, no = int(ps.struct.n_samples), int(ps.struct.n_obs)
     d_mean = torch.full((no,), float("nan"), dtype=torch.float64, device=dev)
@@ -62,6 +62,23 @@ def test_noalloc_matches_run_on_two_calls(handle):
     check_same(first, L.tepai_run(handle, L.ProblemStruct(big)))
     check_same(second, L.tepai_run(handle, L.ProblemStruct(small)))
     assert max(first["stats"]["max_bond"]) > 4
+
+
+def test_noalloc_mixed_path_and_truncated_shared_start(handle):
+    # the mixed path, from a shared chi = 16 start that the cap-4 and cap-8
+    # samples truncate on copy (the start kernel runs in the fixed array too)
+    from oracle.mps import MPS
+    init = ti.random_mps(12, 16, seed=9)
+    m = MPS.from_initial(init)
+    while m.centre < 5:
+        m.shift(m.centre, +1)
+    init = ti.InitialMPS(tensors=tuple(m.A), centre=5, qubit_at=init.qubit_at)
+    p = ti.small_ring(12, seed=4, T=0.3, N=6, delta=math.pi / 16, chi=16, n_samples=6)
+    p = p.with_(initial_mps=init, chi_per_sample=(4, 8, 16, 4, 8, 16))
+    print("no-alloc: mixed path, shared chi=16 start, caps 4/8/16", flush=True)
+    a = run_noalloc(handle, p, precision=1)
+    check_same(a, L.tepai_run(handle, L.ProblemStruct(p, precision=1)))
+    assert list(a["stats"]["max_bond"]) == [4, 8, 16, 4, 8, 16]
 
 
 def test_noalloc_batches_through_the_array(handle):

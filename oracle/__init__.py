@@ -10,10 +10,16 @@ computes, written from the paper:
                   eq. overhead-bound).
 * ``sampler``     TE-PAI circuit sampling (protocol steps 1-2, sec. "TE-PAI").
 * ``schedule``    the MPS operation schedule of one sampled circuit (two-site
-                  updates, centre shifts, SWAP routing of the wrap bond).
+                  updates, fused runs or one update per gate, centre shifts,
+                  SWAP routing of the wrap bond, truncation of a shared
+                  start wider than the sample's cap).
 * ``mps``         mixed-canonical MPS simulator with truncated SVD
                   (sec. "Resource model and cost metrics": bond-dimension and
-                  truncation paragraphs).
+                  truncation paragraphs), the near-tie bound of a cap cut and
+                  a perturbed mode that measures a trajectory's rounding
+                  sensitivity.
+* ``trotter``     the deterministic product-formula circuit and the shared
+                  Trotter state of the hybrid start (sec. "Implementation").
 * ``dense``       dense state-vector references: exact circuit, Trotter,
                   exp(-iHT), and a dense replay of the MPS schedule that
                   performs each truncation as a Schmidt cut of the full state.

@@ -133,6 +133,10 @@ def schedule_state(problem, ops) -> np.ndarray:
             c, d = op[1], op[2]
             bond = c if d > 0 else c - 1
             psi = schmidt_cut(psi, bond, 1 << 30, cut, renormalise=False)
+        else:
+            # ("truncate", chi) only opens the schedule of a shared start,
+            # which this replay (from a basis state) does not take
+            raise ValueError(f"dense replay has no operation {op[0]!r}")
     return psi
 
 

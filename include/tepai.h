@@ -218,7 +218,11 @@ typedef struct tepai_batch tepai_batch;
 typedef struct tepai_step_graph tepai_step_graph;
 
 /* Create a handle bound to HIP device `device`.  Fails with TEPAI_EDEVICE
- * when the device is absent or is not gfx950. */
+ * when the device is absent or is not gfx950.  The first call on a device
+ * also looks up the device address of the fixed array that
+ * tepai_run_noalloc works in (which loads it on that device); a failed
+ * lookup leaves the handle usable for every other call.  The caller's
+ * current device is left as it was. */
 tepai_status tepai_create(tepai_handle** out, int device);
 void tepai_destroy(tepai_handle* h);
 /* Message of the last failure on this handle ("" if none).  Valid until the

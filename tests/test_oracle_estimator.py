@@ -104,6 +104,47 @@ def test_estimate_formulae():
     assert np.allclose(cv, x.var(0, ddof=1) / 4)
 
 
+def test_configuration_variance_closed_form():
+    """Statement 2's configuration variance against its exact value.
+
+    For H = c X0 X1 on |00> the signed per-circuit value is v = cos(b Delta)
+    with b ~ Binomial(N, p_B) (a pi setting flips both the sign of g_l and
+    <Z0>), so Var[v] = (1 + Re[(p_A + p_pi + p_B e^{2i Delta})^N]) / 2
+    - (cos(2cT) / ||g||_1)^2.  At T = 2, Delta = pi/4 the weight is
+    ||g||_1 = 3.35, so dividing the sample variance by ||g||_1 instead of its
+    square, or not centring it, is off by far more than the 10% allowed for
+    2000 samples (the relative spread of the estimate is ~2%).
+    """
+    p = single_term_problem(T=2.0, delta=math.pi / 4, ns=2000, seed=1)
+    t = pai.build_table(p)
+    p1, p2, p3 = t.rows[0].p
+    g1 = math.exp(t.log_g1())
+    assert g1 > 3
+    mean_v = math.cos(2 * 0.8 * p.total_time) / g1
+    ev2 = 0.5 * (1 + (((p1 + p3) + p2 * np.exp(2j * p.delta)) ** p.trotter_steps).real)
+    exact = ev2 - mean_v ** 2
+    r = run(p)
+    assert abs(r.config_var[0] / exact - 1) < 0.1, (r.config_var, exact)
+    # eq. config_var: Var[x] = ||g||_1^2 Var[v], so N_s SE^2 = ||g||_1^2 cv
+    assert abs(p.n_samples * r.std_err[0] ** 2 - g1 ** 2 * r.config_var[0]) < 1e-12 * g1 ** 2
+
+
+def test_configuration_variance_bound():
+    """Var[v] <= 1 for |v| <= 1 (Statement 2); the unbiased sample form
+    reaches N_s/(N_s - 1) exactly when half the values are +1, half -1."""
+    rng = np.random.default_rng(5)
+    for ns in (2, 3, 10, 101):
+        g1 = 7.5
+        vals = rng.uniform(-1, 1, size=(ns, 3))
+        w = g1 * rng.choice([-1.0, 1.0], size=ns)
+        _, _, cv = estimate(vals, w)
+        assert np.all(cv <= ns / (ns - 1) + 1e-12)
+    ns = 10
+    vals = np.array([[1.0], [-1.0]] * (ns // 2))
+    _, _, cv = estimate(vals, np.full(ns, 4.0))
+    assert abs(cv[0] - ns / (ns - 1)) < 1e-12
+
+
 def test_cfg1_estimate_agrees_with_dense_trotter():
     """cfg1 (n=8, chi=16 exact, 200 samples) lands within 4 SE of the Trotter value."""
     p = ti.config(1)

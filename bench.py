@@ -127,6 +127,10 @@ def parse():
     ap.add_argument("--per-gate", action="store_true",
                     help="truncation workload: one truncated update per sampled gate "
                          "(TEPAI_PER_GATE) instead of one per same-pair run")
+    ap.add_argument("--work-queue", action="store_true",
+                    help="batching and hybrid workloads: evolve on one workgroup per CU "
+                         "taking samples from a counter (TEPAI_WORK_QUEUE) instead of one "
+                         "workgroup per sample")
     ap.add_argument("--delta-log2", type=int, default=12,
                     help="truncation workload: PAI angle Delta = pi / 2^k")
     return ap.parse_args()
@@ -274,7 +278,7 @@ def cpu_baseline_saturated(seconds, updates_per_sample, shifts_per_sample, windo
 
 
 # ----------------------------------------------------------------- GPU run
-def run_path(L, h, p, precision, J, K, W, B, match=None, autotune=None):
+def run_path(L, h, p, precision, J, K, W, B, match=None, autotune=None, work_queue=False):
     """W warm-up and K timed steps of one precision path on a fresh batch.
 
     ``match`` (<= K): also report the rate over the first ``match`` timed
@@ -284,7 +288,7 @@ def run_path(L, h, p, precision, J, K, W, B, match=None, autotune=None):
     import numpy as np
     import torch
     dev = torch.device("cuda", 0)
-    ps = L.ProblemStruct(p, precision=precision)
+    ps = L.ProblemStruct(p, precision=precision, work_queue=work_queue)
     stream = torch.cuda.current_stream(dev)
     b = L.Batch(h, ps, 0, B, stream=stream)
     n_obs = ps.n_obs
@@ -514,7 +518,7 @@ def hybrid_experiment(L, h, a):
     if (W + K) * J > p.trotter_steps:
         raise SystemExit("warmup + steps exceed the circuit")
     precision = L.TEPAI_FP32_MIXED if a.hybrid_precision == "mixed" else L.TEPAI_FP64
-    ps = L.ProblemStruct(p, precision=precision)
+    ps = L.ProblemStruct(p, precision=precision, work_queue=a.work_queue)
     b = L.Batch(h, ps, 0, B, stream=stream)
     n_obs = ps.n_obs
     vals = torch.empty(B * n_obs, dtype=torch.float64, device=dev)
@@ -566,7 +570,9 @@ def hybrid_experiment(L, h, a):
                                f"t0={t0_time:g} (N0={n0}, chi={a.pre_cap}) on the GPU, then TE-PAI "
                                "T=2, N=1024, Delta=pi/512, caps " + ("16/32/64 in turn" if a.cycle_caps else "64/32/16 by thirds") + " (a cap below the shared state's bonds truncates its copy), Neel start of the segment",
                    "batch_samples": B, "trotter_steps_per_step": J,
-                   "timed_trotter_steps": [W * J, (W + K) * J]},
+                   "timed_trotter_steps": [W * J, (W + K) * J],
+                   "schedule": ("work queue, one workgroup per CU" if a.work_queue
+                                else "one workgroup per sample")},
         "trotter_segment": {"seconds": prep_s, "steps": n0, "updates": int(prep_stats["updates"][0]),
                             "max_bond": int(prep_stats["max_bond"][0]),
                             "shared_state_bonds_max": max(shared.bonds())},
@@ -593,7 +599,9 @@ def batching_experiment(L, h, a):
     B samples (default 2048, eight per CU) resident in one batch on the
     mixed path.  One workgroup runs one sample; the library launches the
     slots by decreasing cap, and a CU that finishes a small-cap sample takes
-    the next slot, so the hardware scheduler packs the uneven work.  The
+    the next slot, so the hardware scheduler packs the uneven work
+    (--work-queue: one workgroup per CU takes the slots from a counter in
+    the same order instead).  The
     timed window starts at Trotter step --start-step (96) as in the
     throughput step; value = B K J / N / t as there."""
     import tepai_inputs as ti
@@ -604,7 +612,9 @@ def batching_experiment(L, h, a):
     p = base.with_(n_samples=B, chi_per_sample=base.chi_per_sample[:B])
     if (W + K) * J > p.trotter_steps:
         raise SystemExit("warmup + steps exceed the circuit")
-    r = run_path(L, h, p, L.TEPAI_FP32_MIXED, J, K, W, B)
+    r = run_path(L, h, p, L.TEPAI_FP32_MIXED, J, K, W, B, work_queue=a.work_queue)
+    kernel = ("evolve_queue_kernel<4, true> (mixed, work queue)" if a.work_queue
+              else "evolve_kernel<4, true> (mixed)")
     return {
         "metric": "TE-PAI MPS samples/s, n=64 XXZ ring, caps 32/64/128 by sample (batching)",
         "value": r["value"],
@@ -618,7 +628,9 @@ def batching_experiment(L, h, a):
                                "Delta=pi/256, caps (32, 64, 128)[s mod 3], Neel, <Z_i> all i + "
                                "<Z_0 Z_32>",
                    "batch_samples": B, "trotter_steps_per_step": J,
-                   "timed_trotter_steps": [W * J, (W + K) * J]},
+                   "timed_trotter_steps": [W * J, (W + K) * J],
+                   "schedule": ("work queue, one workgroup per CU" if a.work_queue
+                                else "one workgroup per sample")},
         "gates_per_s": r["gates_per_s"],
         "updates_per_s": r["updates_per_s"],
         "sum_chi3_per_s": r["sum_chi3_per_s"],
@@ -626,7 +638,7 @@ def batching_experiment(L, h, a):
         "sum_chi3_per_sample_in_window": r["sum_chi3_per_sample"],
         "roofline": {"bound": "alu", "achieved": r["achieved"], "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": r["achieved"] / FP64_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "evolve_kernel<4, true> (mixed)",
+                     "traffic": None, "kernel": kernel,
                      "kernel_ms_per_launch": r["kernel_ms_per_launch"],
                      "flops_per_launch": r["flops_per_launch"]},
     }

@@ -99,6 +99,14 @@ enum { TEPAI_TROTTER = 2u };
  *   truncation both forms give the same state.  Combines with the other
  *   flags. */
 enum { TEPAI_PER_GATE = 4u };
+/* TEPAI_WORK_QUEUE: scheduling only (sec. "Circuit parallelisation": the
+ *   samples are independent).  A batch's evolve steps run on about one
+ *   workgroup per compute unit, each taking the next sample from a counter
+ *   in the workspace, in the batch's launch order (decreasing bond cap),
+ *   instead of one workgroup per sample.  Results are bitwise those without
+ *   the flag; it matters for batches with many more samples than compute
+ *   units and mixed caps.  Combines with the other flags. */
+enum { TEPAI_WORK_QUEUE = 8u };
 
 /* Storage / arithmetic precision of the MPS path.
  * TEPAI_FP64: complex128 site tensors and FP64 throughout (the Jacobi skips
@@ -186,7 +194,7 @@ typedef struct {
   uint32_t n_strings;
   const tepai_pauli_string* strings;
   uint32_t precision;           /* TEPAI_FP64 or TEPAI_FP32_MIXED */
-  uint32_t flags;               /* TEPAI_NO_PI or TEPAI_TROTTER, | TEPAI_PER_GATE */
+  uint32_t flags;               /* TEPAI_NO_PI or TEPAI_TROTTER, | TEPAI_PER_GATE | TEPAI_WORK_QUEUE */
   const tepai_mps* initial_mps; /* NULL: start from initial_bits */
 } tepai_problem;
 

@@ -25,6 +25,7 @@ TEPAI_FP32_MIXED = 1
 TEPAI_NO_PI = 1
 TEPAI_TROTTER = 2
 TEPAI_PER_GATE = 4
+TEPAI_WORK_QUEUE = 8
 TEPAI_ENUMERIC = -5
 TEPAI_SAMPLE_NONFINITE = 1
 TEPAI_SAMPLE_NONCONVERGED = 2
@@ -149,7 +150,7 @@ class ProblemStruct:
     """A tepai_problem plus the host arrays it points to (kept alive here)."""
 
     def __init__(self, problem, chi_per_sample: Optional[Sequence[int]] = None,
-                 precision: int = TEPAI_FP64):
+                 precision: int = TEPAI_FP64, work_queue: bool = False):
         p = problem
         if len(p.initial_bits) != p.n_qubits:
             raise ValueError("initial_bits must hold one character per qubit")
@@ -201,7 +202,8 @@ class ProblemStruct:
         s.precision = int(precision)
         s.flags = ((TEPAI_NO_PI if getattr(p, "no_pi", False) else 0)
                    | (TEPAI_TROTTER if getattr(p, "trotter", False) else 0)
-                   | (TEPAI_PER_GATE if getattr(p, "per_gate", False) else 0))
+                   | (TEPAI_PER_GATE if getattr(p, "per_gate", False) else 0)
+                   | (TEPAI_WORK_QUEUE if work_queue else 0))
         init = getattr(p, "initial_mps", None)
         s.initial_mps = None
         if init is not None:

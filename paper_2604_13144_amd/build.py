@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtepai.so")
-SOURCES = ["kernels.hip", "host.hip"]
+SOURCES = ["kernels.hip", "queue.hip", "host.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

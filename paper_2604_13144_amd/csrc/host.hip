@@ -238,7 +238,7 @@ tepai_status validate(tepai_handle* h, const tepai_problem* p) {
   }
   if (p->precision != TEPAI_FP64 && p->precision != TEPAI_FP32_MIXED)
     return fail(h, TEPAI_EINVAL, "unsupported precision");
-  if ((p->flags & ~(uint32_t)(TEPAI_NO_PI | TEPAI_TROTTER | TEPAI_PER_GATE)) != 0)
+  if ((p->flags & ~(uint32_t)(TEPAI_NO_PI | TEPAI_TROTTER | TEPAI_PER_GATE | TEPAI_WORK_QUEUE)) != 0)
     return fail(h, TEPAI_EINVAL, "unsupported flags");
   if ((p->flags & TEPAI_NO_PI) && (p->flags & TEPAI_TROTTER))
     return fail(h, TEPAI_EINVAL, "TEPAI_NO_PI and TEPAI_TROTTER exclude each other");
@@ -249,7 +249,7 @@ tepai_status validate(tepai_handle* h, const tepai_problem* p) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t rows, strings, bits, caps, states, tensors, work, init, total;
+  size_t rows, strings, bits, caps, queue, states, tensors, work, init, total;
   uint64_t site_stride, work_stride;
   uint64_t init_elems;     // packed complex values of the initial MPS (0: none)
 };
@@ -276,6 +276,8 @@ Layout layout(const tepai_problem& p, uint32_t l_eff, uint32_t count) {
   off = align256(off + p.n_qubits);
   L.caps = off;     // per-slot caps, then the launch order of the slots
   off = align256(off + sizeof(uint32_t) * 2 * count);
+  L.queue = off;    // work-queue counter (TEPAI_WORK_QUEUE)
+  off = align256(off + sizeof(uint32_t));
   L.states = off;
   off = align256(off + sizeof(SampleState) * count);
   L.tensors = off;
@@ -308,6 +310,8 @@ struct tepai_batch {
   uint32_t trotter_steps;
   uint32_t layers_done;
   uint32_t n_obs;
+  uint32_t* queue;      // work-queue counter in the workspace; null: one workgroup per slot
+  uint32_t queue_grid;  // workgroups of a work-queue launch (all resident at once)
   // host staging kept alive until destroy (async uploads)
   std::vector<DevRow> rows;
   std::vector<DevString> strings;
@@ -320,6 +324,12 @@ struct tepai_batch {
 };
 
 namespace {
+
+// The evolve launch of a batch, in its scheduling form.
+hipError_t evolve_launch(const tepai_batch* b, uint32_t n_layers) {
+  return b->queue ? launch_evolve_queue(b->args, n_layers, b->queue, b->queue_grid, b->stream)
+                  : launch_evolve(b->args, n_layers, b->stream);
+}
 
 // The batch loop of the synchronous estimator: samples in batches of at most
 // B in the device workspace `ws`, each evolved through all N Trotter steps
@@ -541,6 +551,8 @@ tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_
   b->trotter_steps = p->trotter_steps;
   b->layers_done = 0;
   b->n_obs = p->n_obs;
+  b->queue = nullptr;
+  b->queue_grid = 0;
   b->rows = device_rows(*p, t);
   b->strings.resize(std::max<uint32_t>(p->n_strings, 1));
   for (uint32_t s = 0; s < p->n_strings; ++s) {
@@ -631,7 +643,14 @@ tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_
     a.init_centre = m->centre;
     a.init_max_bond = *std::max_element(m->bond, m->bond + n + 1);
   }
-  hipError_t e = hipMemcpyAsync(ws + lay.rows, b->rows.data(), sizeof(DevRow) * L, hipMemcpyHostToDevice, b->stream);
+  hipError_t e = hipSuccess;
+  if (p->flags & TEPAI_WORK_QUEUE) {
+    // as many workgroups as the device holds at once
+    b->queue = (uint32_t*)(ws + lay.queue);
+    e = evolve_queue_grid(a, h->device, &b->queue_grid);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + lay.rows, b->rows.data(), sizeof(DevRow) * L, hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ws + lay.strings, b->strings.data(), sizeof(DevString) * b->strings.size(), hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess)
@@ -666,7 +685,7 @@ tepai_status tepai_batch_evolve(tepai_batch* b, uint32_t n_layers) {
   if ((uint64_t)b->layers_done + n_layers > b->trotter_steps)
     return fail(b->h, TEPAI_ERANGE, "evolve beyond the last Trotter step");
   TEPAI_HIP(b->h, hipSetDevice(b->h->device));
-  TEPAI_HIP(b->h, launch_evolve(b->args, n_layers, b->stream));
+  TEPAI_HIP(b->h, evolve_launch(b, n_layers));
   b->layers_done += n_layers;
   return TEPAI_OK;
 }
@@ -788,7 +807,7 @@ tepai_status tepai_batch_autotune(tepai_batch* b, uint32_t n_layers, const uint3
   for (uint32_t i = 0; i < n_candidates && e == hipSuccess; ++i) {
     b->args.qr_panel = candidates[i];
     e = hipEventRecord(e0, b->stream);
-    if (e == hipSuccess) e = launch_evolve(b->args, n_layers, b->stream);
+    if (e == hipSuccess) e = evolve_launch(b, n_layers);
     if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float t = 0.0f;
@@ -849,7 +868,7 @@ tepai_status tepai_batch_capture_step(tepai_batch* b, uint32_t n_layers, double*
   g->n_layers = n_layers;
   hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    hipError_t work = launch_evolve(b->args, n_layers, b->stream);
+    hipError_t work = evolve_launch(b, n_layers);
     if (work == hipSuccess) work = launch_observe(b->args, d_values, d_weights, b->stream);
     if (work == hipSuccess)
       work = launch_reduce(b->args.count, b->n_obs, d_values, d_weights, d_mean, d_std_err,

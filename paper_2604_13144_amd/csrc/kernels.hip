@@ -1708,6 +1708,11 @@ __device__ Slot make_slot(const EngineArgs& a, int slot, z2* Jl) {
   return S;
 }
 
+// queue.hip compiles the engine above a second time, with TEPAI_ENGINE_ONLY
+// defined, for the work-queue form of the evolve kernel; the kernels and
+// launchers below belong to this translation unit only.
+#ifndef TEPAI_ENGINE_ONLY
+
 // ---------------------------------------------------------------- kernels
 template <bool MIX>
 __global__ __launch_bounds__(NT) void init_kernel(EngineArgs a) {
@@ -2107,8 +2112,10 @@ __global__ __launch_bounds__(NT) void sample_write_kernel(const DevRow* rows, ui
   }
 }
 
+#endif  // TEPAI_ENGINE_ONLY
 }  // namespace
 
+#ifndef TEPAI_ENGINE_ONLY
 hipError_t launch_init(const EngineArgs& a, hipStream_t s) {
   (void)hipGetLastError();   // an earlier call's error was reported by that call
   if (a.mixed)
@@ -2116,12 +2123,6 @@ hipError_t launch_init(const EngineArgs& a, hipStream_t s) {
   else
     hipLaunchKernelGGL(init_kernel<false>, dim3(a.count), dim3(NT), 0, s, a);
   return hipGetLastError();
-}
-
-// Rows per lane needed for matrices of up to 2 chi_max rows.
-static int rows_per_lane(uint32_t chi_max) {
-  const uint32_t r = 2 * chi_max;
-  return r <= 64 ? 1 : r <= 128 ? 2 : r <= 256 ? 4 : 8;
 }
 
 template <bool MIX>
@@ -2206,5 +2207,7 @@ hipError_t launch_sample_write(const DevRow* rows, uint32_t l_eff, uint64_t seed
                      seed, first_sample, n_draws, d_offsets, d_words);
   return hipGetLastError();
 }
+
+#endif  // TEPAI_ENGINE_ONLY
 
 }  // namespace tepai

@@ -90,10 +90,23 @@ struct EngineArgs {
   uint32_t qr_panel;             // QR steps per panel of lazy trailing updates (1..32)
 };
 
-// Kernel launchers (kernels.hip).
+// Engine instantiation (rows per lane) for matrices of up to 2 chi_max rows.
+inline int rows_per_lane(uint32_t chi_max) {
+  const uint32_t r = 2 * chi_max;
+  return r <= 64 ? 1 : r <= 128 ? 2 : r <= 256 ? 4 : 8;
+}
+
+// Kernel launchers (kernels.hip; the work-queue form in queue.hip).
 hipError_t launch_init(const EngineArgs& a, hipStream_t s);
 hipError_t launch_start(const EngineArgs& a, hipStream_t s);
 hipError_t launch_evolve(const EngineArgs& a, uint32_t n_layers, hipStream_t s);
+// Work-queue form: `grid` workgroups (clamped to [1, count]) take the slots
+// in launch order from the counter at `queue`, which it resets first.
+hipError_t launch_evolve_queue(const EngineArgs& a, uint32_t n_layers, uint32_t* queue,
+                               uint32_t grid, hipStream_t s);
+// Workgroups of the work-queue kernel for these arguments that the device
+// holds at once: resident workgroups per CU times the CU count.
+hipError_t evolve_queue_grid(const EngineArgs& a, int device, uint32_t* grid);
 hipError_t launch_observe(const EngineArgs& a, double* d_values, double* d_weights, hipStream_t s);
 hipError_t launch_reduce(uint64_t count, uint32_t n_obs, const double* v, const double* w,
                          double* mean, double* se, hipStream_t s);

@@ -111,6 +111,28 @@ def test_trotter_and_no_pi_exclude_each_other():
     assert e.value.status == -1
 
 
+def test_work_queue_flag_is_scheduling_only():
+    """TEPAI_WORK_QUEUE combines with every other flag and leaves the PAI
+    table alone; an unknown flag bit is rejected."""
+    for kw in ({}, {"no_pi": True}, {"trotter": True}, {"per_gate": True}):
+        plain = L.ProblemStruct(ti.config(1).with_(**kw))
+        queued = L.ProblemStruct(ti.config(1).with_(**kw), work_queue=True)
+        assert queued.struct.flags == plain.struct.flags | L.TEPAI_WORK_QUEUE == plain.struct.flags | 8
+        L.tepai_validate(None, queued)
+        a, b = L.tepai_pai_table(None, plain), L.tepai_pai_table(None, queued)
+        for key in a:
+            assert np.array_equal(np.asarray(a[key]), np.asarray(b[key])), key
+        # the counter takes one 256-byte block of the workspace, whatever the batch
+        for n in (1, 300):
+            assert (L.tepai_workspace_size(None, queued, n)
+                    == L.tepai_workspace_size(None, plain, n))
+    ps = L.ProblemStruct(ti.config(1))
+    ps.struct.flags = 16
+    with pytest.raises(L.TepaiError) as e:
+        L.tepai_validate(None, ps)
+    assert e.value.status == -1
+
+
 def bad(**kw):
     return ti.config(1).with_(**kw)
 

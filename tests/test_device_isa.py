@@ -19,13 +19,14 @@ LLVM_MC = "/opt/rocm/llvm/bin/llvm-mc"
 
 @pytest.mark.slow
 @pytest.mark.skipif(not os.path.exists(LLVM_MC), reason="llvm-mc not installed")
-def test_device_assembly_is_encodable():
+@pytest.mark.parametrize("source", ["kernels.hip", "queue.hip"])
+def test_device_assembly_is_encodable(source):
     flags = [f for f in build.HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
     with tempfile.TemporaryDirectory() as d:
         asm = os.path.join(d, "kernels.s")
         cmd = [build.hipcc(), *flags, "--cuda-device-only", "-S",
                "-I", build.INCLUDE, "-I", build.CSRC,
-               os.path.join(build.CSRC, "kernels.hip"), "-o", asm]
+               os.path.join(build.CSRC, source), "-o", asm]
         res = subprocess.run(cmd, capture_output=True, text=True)
         assert res.returncode == 0, res.stderr[-2000:]
         res = subprocess.run([LLVM_MC, "-triple=amdgcn-amd-amdhsa", "-mcpu=gfx950",

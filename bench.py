@@ -581,7 +581,8 @@ def hybrid_experiment(L, h, a):
         "series_t_Z0_se_halfZZ_se": series,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "evolve_kernel<2, %s>" % ("true" if precision == L.TEPAI_FP32_MIXED else "false"),
+                     "kernel": "%s<2, %s>" % ("evolve_queue_kernel" if a.work_queue else "evolve_kernel",
+                                               "true" if precision == L.TEPAI_FP32_MIXED else "false"),
                      "kernel_ms_per_launch": evolve_ms / K,
                      "flops_per_launch": d["nominal_flops"] / K},
     }

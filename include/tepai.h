@@ -280,7 +280,10 @@ tepai_status tepai_batch_create(tepai_handle* h, const tepai_problem* p, uint64_
                                 uint32_t count, void* workspace, size_t ws_bytes,
                                 void* hip_stream, tepai_batch** out);
 /* Apply the next `n_layers` Trotter steps of every sample's sampled circuit
- * (sampling fused: each sample draws its own gate settings). */
+ * (sampling fused: each sample draws its own gate settings).  Under
+ * TEPAI_WORK_QUEUE this queues two kernels: one zeroes the counter in the
+ * workspace, then the workgroups of the second take the slots from it, so
+ * steps of one batch must not run concurrently on two streams. */
 tepai_status tepai_batch_evolve(tepai_batch* b, uint32_t n_layers);
 /* Read out the observables of every sample at its current step j:
  * d_values[s * n_obs + o] = <O_o> of sample s (normalised state), and
